@@ -1,0 +1,217 @@
+// bp10.hpp -- BP1.0: mass operator y = I^T J I u (Sec. "Benchmark Problem 1",
+// Alg. 1-3).
+//
+// Thread layout: one thread per (a,b) column of the Ng x Ng Gauss grid of an
+// element.  The six one-direction contractions run as
+//   r-interpolation      LDS u[k][j][*]   -> LDS T[k][j][a]      threads (a,j)
+//   s-interpolation      LDS T[k][*][a]   -> registers T2[k]     threads (a,b)
+//   t-interpolation, scaling by wJ, t-projection, all in registers (a,b)
+//   s-projection         LDS V[k][*][a]   -> LDS W[k][j][a]      threads (a,j)
+//   r-projection         LDS W[k][j][*]   -> global y[k][j][i]   threads (i,j)
+// with four workgroup barriers per element group (after staging u, after each
+// LDS-to-LDS phase).  The t-direction never touches LDS, so each Gauss column
+// is interpolated, scaled and projected back inside one thread.
+#pragma once
+
+#include "bp35.hpp"
+
+namespace fem {
+
+template <int NQ, int EPB, class TS>
+__global__ __launch_bounds__(threads_for(0, NQ, EPB)) void bp10_kernel(
+    int64_t E, int64_t ngroups, const double *__restrict__ I1d, const TS *__restrict__ wJ,
+    const TS *__restrict__ u, typename output_of<TS>::type *__restrict__ y,
+    typename compute_of<TS>::type beta, typename compute_of<TS>::type oscale)
+{
+    using TC = typename compute_of<TS>::type;
+    using TY = typename output_of<TS>::type;
+    constexpr int NG = NQ + 1;
+    constexpr int NP = NQ * NQ * NQ;
+    constexpr int NPG = NG * NG * NG;
+    constexpr int NCG = NG * NG;
+    constexpr int PQ = lds_row(NQ, sizeof(TC));
+    constexpr int PG = lds_row(NG, sizeof(TC));
+    constexpr int SU = NQ * NQ * PQ;   // u[k][j][i]
+    constexpr int SA = NQ * NQ * PG;   // T[k][j][a] and W[k][j][a]
+    constexpr int SB = NQ * NG * PG;   // V[k][b][a]
+    constexpr int SLOT = SU + SA + SB;
+    constexpr bool TREG = NQ <= 8;
+
+    __shared__ TC s_I[NG * NQ];
+    __shared__ TC s_w[EPB * SLOT];
+
+    const int t = threadIdx.x;
+    const int slot = t / NCG;
+    const int col = t - slot * NCG;
+    const bool lane = slot < EPB;
+    const int sl = lane ? slot : 0;
+    // (a,b) on the Gauss grid; the same thread is (a,jj) with jj = b in the
+    // half-projected phases and (i,j) in the GLL phase.
+    const int a = col % NG, b = col / NG;
+    const int i4 = col % NQ, j4 = col / NQ;
+    const bool ph13 = lane && b < NQ;          // (a, j) threads
+    const bool ph4 = lane && col < NQ * NQ;    // (i, j) threads
+
+    stage_table(s_I, I1d, NG * NQ);
+    __syncthreads();
+
+    TabVec<NQ, TREG, TC> Ia, Ib;    // I[a][*], I[b][*]
+    TabVec<NG, TREG, TC> Icj, Ici;  // I[*][b] (b as the GLL index j), I[*][i4]
+    Ia.init(s_I, a * NQ, 1);
+    Ib.init(s_I, (b < NG ? b : 0) * NQ, 1);
+    Icj.init(s_I, b < NQ ? b : 0, NQ);
+    Ici.init(s_I, i4, NQ);
+
+    TC *su = s_w + sl * SLOT;
+    TC *sa = su + SU;
+    TC *sb = sa + SA;
+
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t e0 = g * EPB;
+        // stage u of the group's elements (contiguous in global memory)
+        {
+            const int64_t nvalid = (E - e0) < EPB ? (E - e0) : EPB;
+            const int total = static_cast<int>(nvalid) * NP;
+            const TS *ug = u + e0 * NP;
+            for (int x = t; x < total; x += blockDim.x) {
+                const int s = x / NP, n = x - s * NP;
+                const int k = n / (NQ * NQ), r = n - k * NQ * NQ;
+                const int jj = r / NQ, ii = r - jj * NQ;
+                s_w[s * SLOT + k * NQ * PQ + jj * PQ + ii] = ld<TC>(ug, x);
+            }
+        }
+        const int64_t e = e0 + slot;
+        const bool ok = lane && e < E;
+        __syncthreads();
+
+        // r-interpolation: T[k][j][a] = sum_i I[a][i] u[k][j][i]
+        if (ph13) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const TC *row = su + k * NQ * PQ + b * PQ;
+                TC s = 0;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) s += Ia[m] * row[m];
+                sa[k * NQ * PG + b * PG + a] = s;
+            }
+        }
+        __syncthreads();
+
+        // s-interpolation into registers, then the whole t-direction.
+        TC V[NQ];
+        {
+            TC T2[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const TC *cl = sa + k * NQ * PG + a;   // T[k][*][a]
+                TC s = 0;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) s += Ib[m] * cl[m * PG];
+                T2[k] = s;
+            }
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) V[k] = 0;
+            const TS *wJe = wJ + (ok ? e : 0) * NPG + col;
+#pragma unroll
+            for (int c = 0; c < NG; ++c) {
+                TC q = 0;
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) q += uniform_entry(I1d, s_I, c * NQ + k) * T2[k];
+                const TC wq = ok ? q * ld_stream<TC>(wJe, c * NCG) : TC(0);
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) V[k] += uniform_entry(I1d, s_I, c * NQ + k) * wq;
+            }
+        }
+        if (lane) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) sb[k * NG * PG + b * PG + a] = V[k];
+        }
+        __syncthreads();
+
+        // s-projection: W[k][j][a] = sum_b I[b][j] V[k][b][a]
+        if (ph13) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const TC *cl = sb + k * NG * PG + a;
+                TC s = 0;
+#pragma unroll
+                for (int m = 0; m < NG; ++m) s += Icj[m] * cl[m * PG];
+                sa[k * NQ * PG + b * PG + a] = s;
+            }
+        }
+        __syncthreads();
+
+        // r-projection: y[k][j][i] = sum_a I[a][i] W[k][j][a]
+        if (ph4 && ok) {
+            const int64_t base = e * NP + j4 * NQ + i4;
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const TC *row = sa + k * NQ * PG + j4 * PG;
+                TC s = 0;
+#pragma unroll
+                for (int m = 0; m < NG; ++m) s += Ici[m] * row[m];
+                s *= oscale;
+                const int64_t idx = base + k * NQ * NQ;
+                if (beta != TC(0)) s += beta * static_cast<TC>(y[idx]);
+                y[idx] = static_cast<TY>(s);
+            }
+        }
+        // The next group stages u only into s_u (read in the r-interpolation of
+        // this group, which all lanes finished two barriers ago) and then
+        // passes a barrier before sa is rewritten, so no barrier is needed here.
+    }
+}
+
+template <int NQ, int EPB, class TS>
+hipError_t bp10_launch_t(const ApplyArgs &a, hipStream_t s)
+{
+    using TC = typename compute_of<TS>::type;
+    using TY = typename output_of<TS>::type;
+    const int64_t ngroups = (a.E + EPB - 1) / EPB;
+    int64_t grid = ngroups;
+    if (a.grid_cap > 0 && grid > a.grid_cap) grid = a.grid_cap;
+    if (grid < 1) return hipSuccess;
+    const TC oscale = (a.prec == P_F16) ? TC(1.0 / a.geo_scale) : TC(1);
+    hipLaunchKernelGGL((bp10_kernel<NQ, EPB, TS>), dim3(static_cast<unsigned>(grid)),
+                       dim3(threads_for(0, NQ, EPB)), 0, s, a.E, ngroups, a.I1d,
+                       static_cast<const TS *>(a.wJ), static_cast<const TS *>(a.u),
+                       static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale);
+    return hipGetLastError();
+}
+
+template <int NQ, class TS>
+hipError_t bp10_launch_nq(const ApplyArgs &a, hipStream_t s)
+{
+    constexpr auto ch = epb_choices(0, NQ);
+    const int epb = a.epb > 0 ? a.epb : epb_default(0, NQ);
+    if (epb == ch[0]) return bp10_launch_t<NQ, ch[0], TS>(a, s);
+    if constexpr (ch[1] > 0) if (epb == ch[1]) return bp10_launch_t<NQ, ch[1], TS>(a, s);
+    if constexpr (ch[2] > 0) if (epb == ch[2]) return bp10_launch_t<NQ, ch[2], TS>(a, s);
+    if constexpr (ch[3] > 0) if (epb == ch[3]) return bp10_launch_t<NQ, ch[3], TS>(a, s);
+    return hipErrorInvalidConfiguration;
+}
+
+template <class TS>
+hipError_t bp10_launch(const ApplyArgs &a, hipStream_t s)
+{
+    switch (a.N + 1) {
+    case 2: return bp10_launch_nq<2, TS>(a, s);
+    case 3: return bp10_launch_nq<3, TS>(a, s);
+    case 4: return bp10_launch_nq<4, TS>(a, s);
+    case 5: return bp10_launch_nq<5, TS>(a, s);
+    case 6: return bp10_launch_nq<6, TS>(a, s);
+    case 7: return bp10_launch_nq<7, TS>(a, s);
+    case 8: return bp10_launch_nq<8, TS>(a, s);
+    case 9: return bp10_launch_nq<9, TS>(a, s);
+    case 10: return bp10_launch_nq<10, TS>(a, s);
+    case 11: return bp10_launch_nq<11, TS>(a, s);
+    case 12: return bp10_launch_nq<12, TS>(a, s);
+    case 13: return bp10_launch_nq<13, TS>(a, s);
+    case 14: return bp10_launch_nq<14, TS>(a, s);
+    case 15: return bp10_launch_nq<15, TS>(a, s);
+    case 16: return bp10_launch_nq<16, TS>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fem

@@ -1,0 +1,6 @@
+// BP1.0 kernels with bf16_t storage.
+#include "bp10.hpp"
+
+namespace fem {
+hipError_t launch_bp10_bf16(const ApplyArgs &a, hipStream_t s) { return bp10_launch<bf16_t>(a, s); }
+}  // namespace fem

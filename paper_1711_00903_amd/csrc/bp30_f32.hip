@@ -1,0 +1,6 @@
+// BP3.0 kernels with float storage.
+#include "bp30.hpp"
+
+namespace fem {
+hipError_t launch_bp30_f32(const ApplyArgs &a, hipStream_t s) { return bp30_launch<float>(a, s); }
+}  // namespace fem

@@ -1,0 +1,220 @@
+// bp35.hpp -- BP3.5: collocated screened-Poisson operator on GLL nodes,
+// y = (D^T G D + lambda J) u (Sec. "Benchmark Problem 3.5", Alg. 4).
+//
+// Thread layout: thread (i,j) of an element owns the column of nodes (i,j,k),
+// k = 0..Nq-1, in registers (the z-sweep).  The t-derivative and its
+// transpose never leave the registers; the r- and s-contractions read whole
+// rows of a padded LDS volume.  Two workgroup barriers per element group:
+// after u is staged, and after the weighted gradients (wr, ws) are staged.
+#pragma once
+
+#include "fem_device.hpp"
+#include "launch.hpp"
+#include "tiles.hpp"
+
+namespace fem {
+
+// Vector of Nq table entries a thread uses in a contraction: either copied
+// into registers once, or read from the LDS copy of the table on each use.
+template <int LEN, bool REG, class TC>
+struct TabVec {
+    TC v[REG ? LEN : 1];
+    const TC *p;
+    int stride;
+    __device__ __forceinline__ void init(const TC *lds, int base, int stride_)
+    {
+        if constexpr (REG) {
+#pragma unroll
+            for (int m = 0; m < LEN; ++m) v[m] = lds[base + m * stride_];
+        } else {
+            p = lds + base;
+            stride = stride_;
+        }
+    }
+    __device__ __forceinline__ TC operator[](int m) const
+    {
+        if constexpr (REG) return v[m];
+        else return p[m * stride];
+    }
+};
+
+// Table entry that is the same for every lane (index known at compile time):
+// FP64 tables are read straight from global memory (scalar loads); reduced
+// precision reads the LDS copy, which holds the converted values.
+template <class TC>
+__device__ __forceinline__ TC uniform_entry(const double *__restrict__ g, const TC *s, int idx)
+{
+    if constexpr (std::is_same<TC, double>::value) return g[idx];
+    else return s[idx];
+}
+
+template <int NQ, int EPB, class TS>
+__global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
+    int64_t E, int64_t ngroups, const double *__restrict__ D1d, const TS *__restrict__ G,
+    const TS *__restrict__ wJ, typename compute_of<TS>::type lambda, const TS *__restrict__ u,
+    typename output_of<TS>::type *__restrict__ y, typename compute_of<TS>::type beta,
+    typename compute_of<TS>::type oscale)
+{
+    using TC = typename compute_of<TS>::type;
+    using TY = typename output_of<TS>::type;
+    constexpr int NC = NQ * NQ;
+    constexpr int NP = NC * NQ;
+    constexpr int P = lds_row(NQ, sizeof(TC));
+    constexpr int SLAB = NQ * P;
+    constexpr int VOL = NQ * SLAB;
+    constexpr bool TREG = NQ <= 10;
+
+    __shared__ TC s_D[NQ * NQ];
+    __shared__ TC s_u[EPB * VOL];
+    __shared__ TC s_r[EPB * VOL];
+    __shared__ TC s_s[EPB * VOL];
+
+    const int t = threadIdx.x;
+    const int slot = t / NC;
+    const int col = t - slot * NC;
+    const int i = col % NQ;
+    const int j = col / NQ;
+    const bool lane = slot < EPB;
+    const int sl = lane ? slot : 0;
+
+    stage_table(s_D, D1d, NQ * NQ);
+    __syncthreads();
+
+    TabVec<NQ, TREG, TC> Di, Dj, DiT, DjT;   // D[i][m], D[j][m], D[m][i], D[m][j]
+    Di.init(s_D, i * NQ, 1);
+    Dj.init(s_D, j * NQ, 1);
+    DiT.init(s_D, i, NQ);
+    DjT.init(s_D, j, NQ);
+
+    TC *su = s_u + sl * VOL;
+    TC *sr = s_r + sl * VOL;
+    TC *ss = s_s + sl * VOL;
+    const int me = j * P + i;   // this column's offset inside a slab
+
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t e = g * EPB + slot;
+        const bool ok = lane && e < E;
+        const int64_t base = (ok ? e : 0) * NP + col;
+
+        TC uc[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
+        if (lane) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) su[k * SLAB + me] = uc[k];
+        }
+        __syncthreads();
+
+        const TS *Ge = G + (ok ? e : 0) * (6 * NP) + col;
+        TC wt[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            TC qr = 0, qs = 0, qt = 0;
+            const TC *row = su + k * SLAB + j * P;   // u[k][j][*]
+            const TC *cln = su + k * SLAB + i;       // u[k][*][i]
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) {
+                qr += Di[m] * row[m];
+                qs += Dj[m] * cln[m * P];
+                qt += uniform_entry(D1d, s_D, k * NQ + m) * uc[m];
+            }
+            TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
+            if (ok) {
+                const int off = k * NC;
+                grr = ld_stream<TC>(Ge, off + 0 * NP);
+                grs = ld_stream<TC>(Ge, off + 1 * NP);
+                grt = ld_stream<TC>(Ge, off + 2 * NP);
+                gss = ld_stream<TC>(Ge, off + 3 * NP);
+                gst = ld_stream<TC>(Ge, off + 4 * NP);
+                gtt = ld_stream<TC>(Ge, off + 5 * NP);
+            }
+            const TC wr = grr * qr + grs * qs + grt * qt;
+            const TC ws = grs * qr + gss * qs + gst * qt;
+            wt[k] = grt * qr + gst * qs + gtt * qt;
+            if (lane) {
+                sr[k * SLAB + me] = wr;
+                ss[k * SLAB + me] = ws;
+            }
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            TC acc = 0;
+            const TC *rrow = sr + k * SLAB + j * P;   // wr[k][j][*]
+            const TC *scol = ss + k * SLAB + i;       // ws[k][*][i]
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) {
+                acc += DiT[m] * rrow[m];
+                acc += DjT[m] * scol[m * P];
+                acc += uniform_entry(D1d, s_D, m * NQ + k) * wt[m];
+            }
+            if (ok) {
+                const int64_t idx = base + k * NC;
+                if (lambda != TC(0)) acc += lambda * ld<TC>(wJ, idx) * uc[k];
+                acc *= oscale;
+                if (beta != TC(0)) acc += beta * static_cast<TC>(y[idx]);
+                y[idx] = static_cast<TY>(acc);
+            }
+        }
+        // No third barrier: the next group writes s_u only after all lanes have
+        // passed the barrier above (so every read of s_u is done), and writes
+        // s_r / s_s only after its own first barrier, which every lane reaches
+        // after finishing the reads of this group.
+    }
+}
+
+template <int NQ, int EPB, class TS>
+hipError_t bp35_launch_t(const ApplyArgs &a, hipStream_t s)
+{
+    using TC = typename compute_of<TS>::type;
+    using TY = typename output_of<TS>::type;
+    const int64_t ngroups = (a.E + EPB - 1) / EPB;
+    int64_t grid = ngroups;
+    if (a.grid_cap > 0 && grid > a.grid_cap) grid = a.grid_cap;
+    if (grid < 1) return hipSuccess;
+    const TC oscale = (a.prec == P_F16) ? TC(1.0 / a.geo_scale) : TC(1);
+    hipLaunchKernelGGL((bp35_kernel<NQ, EPB, TS>), dim3(static_cast<unsigned>(grid)),
+                       dim3(threads_for(1, NQ, EPB)), 0, s, a.E, ngroups, a.D1d,
+                       static_cast<const TS *>(a.G), static_cast<const TS *>(a.wJ),
+                       static_cast<TC>(a.lambda), static_cast<const TS *>(a.u),
+                       static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale);
+    return hipGetLastError();
+}
+
+template <int NQ, class TS>
+hipError_t bp35_launch_nq(const ApplyArgs &a, hipStream_t s)
+{
+    constexpr auto ch = epb_choices(1, NQ);
+    const int epb = a.epb > 0 ? a.epb : epb_default(1, NQ);
+    if (epb == ch[0]) return bp35_launch_t<NQ, ch[0], TS>(a, s);
+    if constexpr (ch[1] > 0) if (epb == ch[1]) return bp35_launch_t<NQ, ch[1], TS>(a, s);
+    if constexpr (ch[2] > 0) if (epb == ch[2]) return bp35_launch_t<NQ, ch[2], TS>(a, s);
+    if constexpr (ch[3] > 0) if (epb == ch[3]) return bp35_launch_t<NQ, ch[3], TS>(a, s);
+    return hipErrorInvalidConfiguration;
+}
+
+template <class TS>
+hipError_t bp35_launch(const ApplyArgs &a, hipStream_t s)
+{
+    switch (a.N + 1) {
+    case 2: return bp35_launch_nq<2, TS>(a, s);
+    case 3: return bp35_launch_nq<3, TS>(a, s);
+    case 4: return bp35_launch_nq<4, TS>(a, s);
+    case 5: return bp35_launch_nq<5, TS>(a, s);
+    case 6: return bp35_launch_nq<6, TS>(a, s);
+    case 7: return bp35_launch_nq<7, TS>(a, s);
+    case 8: return bp35_launch_nq<8, TS>(a, s);
+    case 9: return bp35_launch_nq<9, TS>(a, s);
+    case 10: return bp35_launch_nq<10, TS>(a, s);
+    case 11: return bp35_launch_nq<11, TS>(a, s);
+    case 12: return bp35_launch_nq<12, TS>(a, s);
+    case 13: return bp35_launch_nq<13, TS>(a, s);
+    case 14: return bp35_launch_nq<14, TS>(a, s);
+    case 15: return bp35_launch_nq<15, TS>(a, s);
+    case 16: return bp35_launch_nq<16, TS>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fem

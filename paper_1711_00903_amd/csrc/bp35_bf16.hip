@@ -1,0 +1,6 @@
+// BP3.5 kernels with bf16_t storage.
+#include "bp35.hpp"
+
+namespace fem {
+hipError_t launch_bp35_bf16(const ApplyArgs &a, hipStream_t s) { return bp35_launch<bf16_t>(a, s); }
+}  // namespace fem

@@ -1,0 +1,323 @@
+// fem_api.cpp -- the extern "C" entry points of libfem (declared in fem.h):
+// argument validation (before anything is enqueued), dispatch to the kernel
+// families by (operator, degree, storage precision), and the process-wide
+// launch-configuration table.
+#include <atomic>
+#include <cstdint>
+#include <utility>
+
+#include "fem.h"
+#include "launch.hpp"
+#include "tiles.hpp"
+
+namespace fem {
+
+hipError_t launch_bp35_f64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_f32(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_bf16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_f16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_f64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_f32(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_bf16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_f16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_f64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_f32(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_bf16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_f16(const ApplyArgs &, hipStream_t);
+
+hipError_t launch_bp35(const ApplyArgs &a, hipStream_t s)
+{
+    switch (a.prec) {
+    case P_F64: return launch_bp35_f64(a, s);
+    case P_F32: return launch_bp35_f32(a, s);
+    case P_BF16: return launch_bp35_bf16(a, s);
+    case P_F16: return launch_bp35_f16(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_bp10(const ApplyArgs &a, hipStream_t s)
+{
+    switch (a.prec) {
+    case P_F64: return launch_bp10_f64(a, s);
+    case P_F32: return launch_bp10_f32(a, s);
+    case P_BF16: return launch_bp10_bf16(a, s);
+    case P_F16: return launch_bp10_f16(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_bp30(const ApplyArgs &a, hipStream_t s)
+{
+    switch (a.prec) {
+    case P_F64: return launch_bp30_f64(a, s);
+    case P_F32: return launch_bp30_f32(a, s);
+    case P_BF16: return launch_bp30_bf16(a, s);
+    case P_F16: return launch_bp30_f16(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static constexpr std::array<int, 4> epb_table(int op, int nq) { return epb_choices(op, nq); }
+
+int supported_epb(int op, int N, int prec, int *out, int cap)
+{
+    (void)prec;
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN) return 0;
+    int cnt = 0;
+    std::array<int, 4> ch{};
+    switch (N + 1) {
+#define FEM_CASE(q) case q: ch = epb_table(op, q); break;
+        FEM_CASE(2) FEM_CASE(3) FEM_CASE(4) FEM_CASE(5) FEM_CASE(6) FEM_CASE(7) FEM_CASE(8)
+        FEM_CASE(9) FEM_CASE(10) FEM_CASE(11) FEM_CASE(12) FEM_CASE(13) FEM_CASE(14)
+        FEM_CASE(15) FEM_CASE(16)
+#undef FEM_CASE
+    default: return 0;
+    }
+    for (int c : ch)
+        if (c > 0) {
+            if (out && cnt < cap) out[cnt] = c;
+            ++cnt;
+        }
+    return cnt;
+}
+
+int default_epb(int op, int N, int prec)
+{
+    (void)prec;
+    return epb_default(op, N + 1);
+}
+
+bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
+{
+    int ch[kMaxEpbChoices];
+    const int n = supported_epb(op, N, prec, ch, kMaxEpbChoices);
+    if (epb == 0) epb = default_epb(op, N, prec);
+    bool found = false;
+    for (int c = 0; c < n; ++c) found |= (ch[c] == epb);
+    if (!found) return false;
+    const int bytes = prec == P_F64 ? 8 : 4;
+    info->threads = threads_for(op, N + 1, epb);
+    info->lds_bytes = lds_bytes(op, N + 1, epb, bytes);
+    return true;
+}
+
+// Process-wide launch configuration: (op, N, prec) -> (epb, grid_cap).
+static std::atomic<int> g_epb[3][kMaxN + 1][4];
+static std::atomic<int> g_cap[3][kMaxN + 1][4];
+
+}  // namespace fem
+
+using namespace fem;
+
+namespace {
+
+constexpr int64_t kMaxElements = 2147483647LL;
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t prec_bytes(int prec)
+{
+    switch (prec) {
+    case FEM_F64: return 8;
+    case FEM_F32: return 4;
+    default: return 2;
+    }
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+int common_checks(int op, int N, int64_t E, int prec, float geo_scale, const void *u, const void *y)
+{
+    if (N < 1 || N > kMaxN) return FEM_ERR_ARG;
+    if (E < 0 || E > kMaxElements) return FEM_ERR_ARG;
+    if (prec < FEM_F64 || prec > FEM_F16) return FEM_ERR_UNSUPPORTED;
+    if (prec == FEM_F16 && !(geo_scale > 0.0f)) return FEM_ERR_ARG;
+    if (E == 0) return FEM_OK;
+    if (!u || !y) return FEM_ERR_ARG;
+    if (!aligned16(u) || !aligned16(y)) return FEM_ERR_ALIGN;
+    const int64_t np = static_cast<int64_t>(N + 1) * (N + 1) * (N + 1);
+    const size_t ybytes = prec == FEM_F64 ? 8 : 4;
+    if (overlap(u, E * np * prec_bytes(prec), y, E * np * ybytes)) return FEM_ERR_ARG;
+    (void)op;
+    return FEM_OK;
+}
+
+int tune_lookup(int op, int N, int prec, int *epb, int *cap)
+{
+    *epb = g_epb[op][N][prec].load(std::memory_order_relaxed);
+    *cap = g_cap[op][N][prec].load(std::memory_order_relaxed);
+    if (*epb == 0) *epb = default_epb(op, N, prec);
+    return FEM_OK;
+}
+
+int finish(hipError_t e) { return e == hipSuccess ? FEM_OK : FEM_ERR_HIP; }
+
+int run_apply(ApplyArgs &a, void *stream)
+{
+    tune_lookup(a.op, a.N, a.prec, &a.epb, &a.grid_cap);
+    KernelInfo ki;
+    if (!kernel_info(a.op, a.N, a.prec, a.epb, &ki)) return FEM_ERR_UNSUPPORTED;
+    if (a.E == 0) return FEM_OK;
+    auto s = static_cast<hipStream_t>(stream);
+    switch (a.op) {
+    case OP_BP10: return finish(launch_bp10(a, s));
+    case OP_BP35: return finish(launch_bp35(a, s));
+    case OP_BP30: return finish(launch_bp30(a, s));
+    default: return FEM_ERR_UNSUPPORTED;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fem_status_str(int status)
+{
+    switch (status) {
+    case FEM_OK: return "ok";
+    case FEM_ERR_ARG: return "invalid argument";
+    case FEM_ERR_UNSUPPORTED: return "unsupported configuration";
+    case FEM_ERR_ALIGN: return "pointer not 16-byte aligned";
+    case FEM_ERR_HIP: return "HIP runtime error";
+    case FEM_ERR_NOT_CONVERGED: return "not converged";
+    case FEM_ERR_BREAKDOWN: return "breakdown";
+    case FEM_ERR_WORKSPACE: return "workspace too small";
+    case FEM_ERR_GEOMETRY: return "non-positive Jacobian";
+    default: return "unknown status";
+    }
+}
+
+int fem_version(void) { return 100; }
+int fem_max_degree(void) { return kMaxN; }
+int64_t fem_max_elements(void) { return kMaxElements; }
+
+int fem_basis_tables(int N, double *r_gll, double *w_gll, double *r_gl, double *w_gl, double *I1d,
+                     double *D1d, double *Dgl)
+{
+    if (N < 1 || N > kMaxN) return FEM_ERR_ARG;
+    return basis_tables(N, r_gll, w_gll, r_gl, w_gl, I1d, D1d, Dgl) ? FEM_ERR_ARG : FEM_OK;
+}
+
+int fem_geometric_factors(int N, int64_t E, int quad, const double *X, void *G, void *wJ, int prec,
+                          float geo_scale, int64_t *bad_count, void *stream)
+{
+    if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
+    if (quad != FEM_QUAD_GLL && quad != FEM_QUAD_GL) return FEM_ERR_ARG;
+    if (prec < FEM_F64 || prec > FEM_F16) return FEM_ERR_UNSUPPORTED;
+    if (prec == FEM_F16 && !(geo_scale > 0.0f)) return FEM_ERR_ARG;
+    if (E == 0) return FEM_OK;
+    if (!X || (!G && !wJ)) return FEM_ERR_ARG;
+    if (!aligned16(X) || (G && !aligned16(G)) || (wJ && !aligned16(wJ))) return FEM_ERR_ALIGN;
+    if (bad_count && (reinterpret_cast<uintptr_t>(bad_count) & 7u)) return FEM_ERR_ALIGN;
+    return finish(launch_geometry(N, E, quad, X, G, wJ, prec, geo_scale, bad_count,
+                                  static_cast<hipStream_t>(stream)));
+}
+
+int fem_node_coords(int N, int64_t E, int quad, const double *X, double *xyz, void *stream)
+{
+    if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
+    if (quad != FEM_QUAD_GLL && quad != FEM_QUAD_GL) return FEM_ERR_ARG;
+    if (E == 0) return FEM_OK;
+    if (!X || !xyz) return FEM_ERR_ARG;
+    if (!aligned16(X) || !aligned16(xyz)) return FEM_ERR_ALIGN;
+    return finish(launch_node_coords(N, E, quad, X, xyz, static_cast<hipStream_t>(stream)));
+}
+
+int fem_mass_apply(int N, int64_t E, const double *I1d, const void *wJ, const void *u, void *y,
+                   double beta, int prec, float geo_scale, void *stream)
+{
+    int st = common_checks(OP_BP10, N, E, prec, geo_scale, u, y);
+    if (st != FEM_OK) return st;
+    if (E > 0) {
+        if (!I1d || !wJ) return FEM_ERR_ARG;
+        if (!aligned16(wJ) || !aligned16(I1d)) return FEM_ERR_ALIGN;
+    }
+    ApplyArgs a{};
+    a.op = OP_BP10; a.N = N; a.E = E; a.I1d = I1d; a.wJ = wJ; a.u = u; a.y = y;
+    a.beta = beta; a.prec = prec; a.geo_scale = geo_scale;
+    return run_apply(a, stream);
+}
+
+int fem_stiff_collocated_apply(int N, int64_t E, const double *D1d, const void *G, const void *wJ,
+                               double lambda, const void *u, void *y, double beta, int prec,
+                               float geo_scale, void *stream)
+{
+    int st = common_checks(OP_BP35, N, E, prec, geo_scale, u, y);
+    if (st != FEM_OK) return st;
+    if (E > 0) {
+        if (!D1d || !G || (lambda != 0.0 && !wJ)) return FEM_ERR_ARG;
+        if (!aligned16(G) || !aligned16(D1d) || (wJ && !aligned16(wJ))) return FEM_ERR_ALIGN;
+    }
+    ApplyArgs a{};
+    a.op = OP_BP35; a.N = N; a.E = E; a.D1d = D1d; a.G = G; a.wJ = wJ; a.lambda = lambda;
+    a.u = u; a.y = y; a.beta = beta; a.prec = prec; a.geo_scale = geo_scale;
+    return run_apply(a, stream);
+}
+
+int fem_stiff_dealiased_apply(int N, int64_t E, const double *I1d, const double *Dgl, const void *G,
+                              const void *wJ, double lambda, const void *u, void *y, double beta,
+                              int prec, float geo_scale, void *stream)
+{
+    int st = common_checks(OP_BP30, N, E, prec, geo_scale, u, y);
+    if (st != FEM_OK) return st;
+    if (E > 0) {
+        if (!I1d || !Dgl || !G || (lambda != 0.0 && !wJ)) return FEM_ERR_ARG;
+        if (!aligned16(G) || !aligned16(I1d) || !aligned16(Dgl) || (wJ && !aligned16(wJ)))
+            return FEM_ERR_ALIGN;
+    }
+    ApplyArgs a{};
+    a.op = OP_BP30; a.N = N; a.E = E; a.I1d = I1d; a.Dgl = Dgl; a.G = G; a.wJ = wJ;
+    a.lambda = lambda; a.u = u; a.y = y; a.beta = beta; a.prec = prec; a.geo_scale = geo_scale;
+    return run_apply(a, stream);
+}
+
+int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (bytes == 0) return FEM_OK;
+    if (!src || !dst || (bytes & 15u)) return FEM_ERR_ARG;
+    if (!aligned16(src) || !aligned16(dst)) return FEM_ERR_ALIGN;
+    if (overlap(src, bytes, dst, bytes)) return FEM_ERR_ARG;
+    return finish(launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
+}
+
+int fem_tune_set(int op, int N, int prec, int epb, int grid_cap)
+{
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3 || epb < 0 || grid_cap < 0)
+        return FEM_ERR_ARG;
+    if (epb != 0) {
+        KernelInfo ki;
+        if (!kernel_info(op, N, prec, epb, &ki)) return FEM_ERR_UNSUPPORTED;
+    }
+    g_epb[op][N][prec].store(epb, std::memory_order_relaxed);
+    g_cap[op][N][prec].store(grid_cap, std::memory_order_relaxed);
+    return FEM_OK;
+}
+
+int fem_tune_get(int op, int N, int prec, int *epb, int *grid_cap)
+{
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3 || !epb || !grid_cap)
+        return FEM_ERR_ARG;
+    return tune_lookup(op, N, prec, epb, grid_cap);
+}
+
+int fem_kernel_info(int op, int N, int prec, int epb, int *threads, int *lds_bytes_out)
+{
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3) return FEM_ERR_ARG;
+    KernelInfo ki;
+    if (!kernel_info(op, N, prec, epb, &ki)) return FEM_ERR_UNSUPPORTED;
+    if (threads) *threads = ki.threads;
+    if (lds_bytes_out) *lds_bytes_out = ki.lds_bytes;
+    return FEM_OK;
+}
+
+int fem_supported_epb(int op, int N, int prec, int *epbs, int cap)
+{
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3 || cap < 0)
+        return -FEM_ERR_ARG;
+    return supported_epb(op, N, prec, epbs, cap);
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// fem_device.hpp -- device-side building blocks shared by the gfx950 kernels:
+// storage types and conversions, the column/slab thread layout, and the
+// launch-shape helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+namespace fem {
+
+// ---------------------------------------------------------------------------
+// Storage types.  u, G and wJ are stored in one of four precisions; FP64
+// storage computes in FP64, the others in FP32.
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+using f16_t = _Float16;
+
+template <class T> struct compute_of { using type = float; };
+template <> struct compute_of<double> { using type = double; };
+
+template <class T> struct output_of { using type = float; };
+template <> struct output_of<double> { using type = double; };
+
+__device__ __forceinline__ double to_compute(double v, double) { return v; }
+__device__ __forceinline__ float to_compute(float v, float) { return v; }
+__device__ __forceinline__ float to_compute(bf16_t v, float)
+{
+    return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
+}
+__device__ __forceinline__ float to_compute(f16_t v, float) { return static_cast<float>(v); }
+
+template <class TC, class TS>
+__device__ __forceinline__ TC ld(const TS *__restrict__ p, int64_t idx)
+{
+    return to_compute(p[idx], TC{});
+}
+
+// Round-to-nearest-even float -> bfloat16 (finite inputs).
+__device__ __forceinline__ bf16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return bf16_t{static_cast<uint16_t>(u >> 16)};
+}
+
+template <class TS> __device__ __forceinline__ TS from_double(double v);
+template <> __device__ __forceinline__ double from_double<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_double<float>(double v) { return static_cast<float>(v); }
+template <> __device__ __forceinline__ bf16_t from_double<bf16_t>(double v) { return to_bf16(static_cast<float>(v)); }
+template <> __device__ __forceinline__ f16_t from_double<f16_t>(double v) { return static_cast<f16_t>(static_cast<float>(v)); }
+
+// Non-temporal load for data that is streamed exactly once (geometric factors):
+// keeps them from evicting the field vectors from the caches.
+template <class TC, class TS>
+__device__ __forceinline__ TC ld_stream(const TS *__restrict__ p, int64_t idx)
+{
+    return to_compute(__builtin_nontemporal_load(p + idx), TC{});
+}
+template <>
+__device__ __forceinline__ float ld_stream<float, bf16_t>(const bf16_t *__restrict__ p, int64_t idx)
+{
+    const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
+    return __uint_as_float(static_cast<uint32_t>(__builtin_nontemporal_load(q + idx)) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Launch shapes.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+constexpr int round_up_wave(int n) { return (n + kWave - 1) / kWave * kWave; }
+
+// Row length (in values) of an LDS slab whose rows hold `n` values of `bytes`
+// bytes.  A thread reads a whole row with the widest aligned LDS reads, and the
+// lanes of a wave read up to n different rows at once: pick the smallest
+// padded length (kept 16-byte aligned for even n) for which those rows start
+// in disjoint groups of the 64 four-byte banks.
+constexpr int bank_conflicts(int P, int n, int bytes)
+{
+    const int words = P * bytes / 4;
+    const int width = (n * bytes % 16 == 0) ? 4 : (bytes >= 8 ? 2 : 1);
+    int worst = 0;
+    for (int b = 0; b < 64; ++b) {
+        int hits = 0;
+        for (int r = 0; r < n && r < 64; ++r) {
+            int start = (r * words) % 64;
+            for (int x = 0; x < width; ++x)
+                if ((start + x) % 64 == b) ++hits;
+        }
+        if (hits > worst) worst = hits;
+    }
+    return worst;
+}
+
+constexpr int lds_row(int n, int bytes)
+{
+    int best = n, best_c = bank_conflicts(n, n, bytes);
+    const int step = (n * bytes % 16 == 0) ? 16 / bytes : 1;
+    for (int P = n + step; P <= n + 4 * step; P += step) {
+        int c = bank_conflicts(P, n, bytes);
+        if (c < best_c) { best = P; best_c = c; }
+    }
+    return best;
+}
+
+// One table (row-major rows x cols of FP64 in global memory) staged in LDS in
+// the compute precision.
+template <class TC>
+__device__ __forceinline__ void stage_table(TC *__restrict__ dst, const double *__restrict__ src,
+                                            int count)
+{
+    for (int t = threadIdx.x; t < count; t += blockDim.x) dst[t] = static_cast<TC>(src[t]);
+}
+
+}  // namespace fem

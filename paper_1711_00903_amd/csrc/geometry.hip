@@ -1,0 +1,204 @@
+// geometry.hip -- set-up kernels: geometric factors and node coordinates of
+// trilinear hexahedra (Problem description section), and the streaming copy
+// that calibrates the empirical bandwidth roofline (Empirical performance
+// model section, eq. globalRoof).
+//
+// Geometry.  Vertex v = a + 2b + 4c sits at reference corner
+// (xi, eta, zeta) = (2a-1, 2b-1, 2c-1); the trilinear map is
+//   x(r,s,t) = 1/8 sum_v X_v (1 + xi_v r)(1 + eta_v s)(1 + zeta_v t).
+// With the covariant vectors a_r = dx/dr, a_s = dx/ds, a_t = dx/dt,
+//   |J| = a_r . (a_s x a_t),
+// and the contravariant vectors grad r = (a_s x a_t)/|J|, grad s = (a_t x a_r)/|J|,
+// grad t = (a_r x a_s)/|J|.  The weighted metric is therefore
+//   G_ab = w |J| grad r_a . grad r_b = w (c_a . c_b) / |J|,
+// with c_r = a_s x a_t, c_s = a_t x a_r, c_t = a_r x a_s.
+#include "fem_device.hpp"
+#include "launch.hpp"
+
+namespace fem {
+
+struct NodeRule {
+    double r[kMaxN + 2];
+    double w[kMaxN + 2];
+};
+
+struct Vec3 {
+    double x, y, z;
+};
+__device__ __forceinline__ Vec3 cross(const Vec3 &p, const Vec3 &q)
+{
+    return {p.y * q.z - p.z * q.y, p.z * q.x - p.x * q.z, p.x * q.y - p.y * q.x};
+}
+__device__ __forceinline__ double dot(const Vec3 &p, const Vec3 &q)
+{
+    return p.x * q.x + p.y * q.y + p.z * q.z;
+}
+
+template <class TS>
+__global__ __launch_bounds__(256) void geometry_kernel(int nq, int64_t E, const double *__restrict__ X,
+                                                       NodeRule rule, TS *__restrict__ G,
+                                                       TS *__restrict__ wJ, double scale,
+                                                       int64_t *__restrict__ bad)
+{
+    const int64_t npq = static_cast<int64_t>(nq) * nq * nq;
+    const int64_t total = E * npq;
+    for (int64_t id = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; id < total;
+         id += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = id / npq;
+        const int n = static_cast<int>(id - e * npq);
+        const int a = n % nq, b = (n / nq) % nq, c = n / (nq * nq);
+        const double r = rule.r[a], s = rule.r[b], t = rule.r[c];
+        const double *Xe = X + 24 * e;
+        Vec3 ar{0, 0, 0}, as{0, 0, 0}, at{0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const double xi = (v & 1) ? 1.0 : -1.0;
+            const double eta = (v & 2) ? 1.0 : -1.0;
+            const double zeta = (v & 4) ? 1.0 : -1.0;
+            const double fr = 0.125 * xi * (1.0 + eta * s) * (1.0 + zeta * t);
+            const double fs = 0.125 * eta * (1.0 + xi * r) * (1.0 + zeta * t);
+            const double ft = 0.125 * zeta * (1.0 + xi * r) * (1.0 + eta * s);
+            const double px = Xe[3 * v], py = Xe[3 * v + 1], pz = Xe[3 * v + 2];
+            ar.x += fr * px; ar.y += fr * py; ar.z += fr * pz;
+            as.x += fs * px; as.y += fs * py; as.z += fs * pz;
+            at.x += ft * px; at.y += ft * py; at.z += ft * pz;
+        }
+        const Vec3 cr = cross(as, at), cs = cross(at, ar), ct = cross(ar, as);
+        const double det = dot(ar, cr);
+        if (!(det > 0.0) && bad) atomicAdd(reinterpret_cast<unsigned long long *>(bad), 1ull);
+        const double w = rule.w[a] * rule.w[b] * rule.w[c];
+        if (wJ) wJ[e * npq + n] = from_double<TS>(scale * w * det);
+        if (G) {
+            const double f = scale * w / det;
+            TS *Ge = G + e * 6 * npq + n;
+            Ge[0 * npq] = from_double<TS>(f * dot(cr, cr));
+            Ge[1 * npq] = from_double<TS>(f * dot(cr, cs));
+            Ge[2 * npq] = from_double<TS>(f * dot(cr, ct));
+            Ge[3 * npq] = from_double<TS>(f * dot(cs, cs));
+            Ge[4 * npq] = from_double<TS>(f * dot(cs, ct));
+            Ge[5 * npq] = from_double<TS>(f * dot(ct, ct));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void node_coords_kernel(int nq, int64_t E, const double *__restrict__ X,
+                                                          NodeRule rule, double *__restrict__ xyz)
+{
+    const int64_t npq = static_cast<int64_t>(nq) * nq * nq;
+    const int64_t total = E * npq;
+    for (int64_t id = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; id < total;
+         id += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = id / npq;
+        const int n = static_cast<int>(id - e * npq);
+        const int a = n % nq, b = (n / nq) % nq, c = n / (nq * nq);
+        const double r = rule.r[a], s = rule.r[b], t = rule.r[c];
+        const double *Xe = X + 24 * e;
+        double x = 0, y = 0, z = 0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const double f = 0.125 * (1.0 + ((v & 1) ? r : -r)) * (1.0 + ((v & 2) ? s : -s)) *
+                             (1.0 + ((v & 4) ? t : -t));
+            x += f * Xe[3 * v];
+            y += f * Xe[3 * v + 1];
+            z += f * Xe[3 * v + 2];
+        }
+        xyz[3 * id] = x;
+        xyz[3 * id + 1] = y;
+        xyz[3 * id + 2] = z;
+    }
+}
+
+static NodeRule make_rule(int N, int quad)
+{
+    NodeRule rule{};
+    if (quad == 0) gauss_lobatto(N, rule.r, rule.w);
+    else gauss_legendre(N + 2, rule.r, rule.w);
+    return rule;
+}
+
+static unsigned grid_for(int64_t total, int threads)
+{
+    int64_t blocks = (total + threads - 1) / threads;
+    const int64_t cap = 256 * 64;   // 64 workgroups per CU is plenty for set-up work
+    if (blocks > cap) blocks = cap;
+    return static_cast<unsigned>(blocks < 1 ? 1 : blocks);
+}
+
+hipError_t launch_geometry(int N, int64_t E, int quad, const double *X, void *G, void *wJ, int prec,
+                           float geo_scale, int64_t *bad, hipStream_t s)
+{
+    const int nq = quad == 0 ? N + 1 : N + 2;
+    const int64_t total = E * nq * nq * nq;
+    if (total == 0) return hipSuccess;
+    const NodeRule rule = make_rule(N, quad);
+    const double scale = prec == P_F16 ? static_cast<double>(geo_scale) : 1.0;
+    const unsigned grid = grid_for(total, 256);
+    switch (prec) {
+    case P_F64:
+        hipLaunchKernelGGL(geometry_kernel<double>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
+                           static_cast<double *>(G), static_cast<double *>(wJ), scale, bad);
+        break;
+    case P_F32:
+        hipLaunchKernelGGL(geometry_kernel<float>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
+                           static_cast<float *>(G), static_cast<float *>(wJ), scale, bad);
+        break;
+    case P_BF16:
+        hipLaunchKernelGGL(geometry_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
+                           static_cast<bf16_t *>(G), static_cast<bf16_t *>(wJ), scale, bad);
+        break;
+    case P_F16:
+        hipLaunchKernelGGL(geometry_kernel<f16_t>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
+                           static_cast<f16_t *>(G), static_cast<f16_t *>(wJ), scale, bad);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_node_coords(int N, int64_t E, int quad, const double *X, double *xyz, hipStream_t s)
+{
+    const int nq = quad == 0 ? N + 1 : N + 2;
+    const int64_t total = E * nq * nq * nq;
+    if (total == 0) return hipSuccess;
+    const NodeRule rule = make_rule(N, quad);
+    hipLaunchKernelGGL(node_coords_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, nq, E, X,
+                       rule, xyz);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy: 16-byte vector loads and stores, four in flight per thread.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                   int64_t n)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const u32x4 v0 = __builtin_nontemporal_load(src + i);
+        const u32x4 v1 = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 v2 = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 v3 = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(v0, dst + i);
+        __builtin_nontemporal_store(v1, dst + i + stride);
+        __builtin_nontemporal_store(v2, dst + i + 2 * stride);
+        __builtin_nontemporal_store(v3, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const int64_t n = static_cast<int64_t>(bytes / 16);
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 4 * 256 - 1) / (4 * 256);
+    const int64_t cap = 256 * 16;   // 16 workgroups of 256 threads per CU
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n);
+    return hipGetLastError();
+}
+
+}  // namespace fem

@@ -1,0 +1,62 @@
+// launch.hpp -- host-side interface between the C ABI (fem_api.cpp) and the
+// kernel translation units.  Plain structs of device pointers and scalars.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace fem {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
+enum Op { OP_BP10 = 0, OP_BP35 = 1, OP_BP30 = 2 };
+
+constexpr int kMaxN = 15;
+constexpr int kMaxEpbChoices = 4;
+
+struct ApplyArgs {
+    int op;
+    int N;
+    int64_t E;
+    const double *I1d;   // (N+2) x (N+1)
+    const double *D1d;   // (N+1) x (N+1)
+    const double *Dgl;   // (N+2) x (N+2)
+    const void *G;       // [E][6][Npq]
+    const void *wJ;      // [E][Npq] or null
+    const void *u;       // [E][Np]
+    void *y;             // [E][Np]
+    double lambda;
+    double beta;
+    float geo_scale;
+    int prec;
+    int epb;             // elements per workgroup, 0 = default
+    int grid_cap;        // max workgroups, 0 = uncapped
+};
+
+struct KernelInfo {
+    int threads;
+    int lds_bytes;
+};
+
+// Each returns a hipError_t from the launch (hipSuccess when enqueued).
+hipError_t launch_bp35(const ApplyArgs &a, hipStream_t s);
+hipError_t launch_bp10(const ApplyArgs &a, hipStream_t s);
+hipError_t launch_bp30(const ApplyArgs &a, hipStream_t s);
+
+// Supported elements-per-workgroup values of (op, N, prec); returns count.
+int supported_epb(int op, int N, int prec, int *out, int cap);
+int default_epb(int op, int N, int prec);
+bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info);
+
+hipError_t launch_geometry(int N, int64_t E, int quad, const double *X, void *G, void *wJ,
+                           int prec, float geo_scale, int64_t *bad, hipStream_t s);
+hipError_t launch_node_coords(int N, int64_t E, int quad, const double *X, double *xyz,
+                              hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// Host-side quadrature and tables (basis.cpp).
+int basis_tables(int N, double *r_gll, double *w_gll, double *r_gl, double *w_gl, double *I1d,
+                 double *D1d, double *Dgl);
+int gauss_lobatto(int N, double *r, double *w);
+int gauss_legendre(int n, double *r, double *w);
+
+}  // namespace fem

@@ -1,0 +1,70 @@
+// tiles.hpp -- launch shapes of the element kernels, usable on host and device.
+//
+// Every kernel maps one thread to one (i,j) column of an element (a vertical
+// line of nodes along t) and packs `epb` elements into one workgroup.  BP3.5
+// works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
+// (the GLL phases use a subset of those threads).
+#pragma once
+
+#include <array>
+
+#include "fem_device.hpp"
+
+namespace fem {
+
+constexpr int kMaxThreads = 512;
+constexpr int kMaxLds = 160 * 1024;   // gfx950 LDS per workgroup
+
+constexpr int columns(int op, int nq) { return op == 1 ? nq * nq : (nq + 1) * (nq + 1); }
+
+// LDS bytes of one workgroup for values of `bytes` bytes (tables included).
+constexpr int lds_bytes(int op, int nq, int epb, int bytes)
+{
+    const int ng = nq + 1;
+    const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
+    if (op == 1) return (nq * nq + 3 * epb * nq * nq * pq) * bytes;
+    if (op == 0) {
+        const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
+        return (ng * nq + epb * slot) * bytes;
+    }
+    const int r1a = nq * nq * pq, r1b = ng * ng * pg, r1c = nq * ng * pg;
+    const int r1 = r1a > r1b ? (r1a > r1c ? r1a : r1c) : (r1b > r1c ? r1b : r1c);
+    const int r2a = nq * nq * pg, r2b = ng * ng * pg;
+    const int r2 = r2a > r2b ? r2a : r2b;
+    const int r3 = ng * ng * pg;
+    return (ng * nq + ng * ng + epb * (r1 + r2 + r3)) * bytes;
+}
+
+constexpr int threads_for(int op, int nq, int epb) { return round_up_wave(columns(op, nq) * epb); }
+
+// Up to four supported elements-per-workgroup values: 1, then those that fill
+// at least 80% of the lanes of the workgroup's waves within the thread and
+// LDS limits (sized for 8-byte values, the largest).
+constexpr std::array<int, 4> epb_choices(int op, int nq)
+{
+    std::array<int, 4> out{0, 0, 0, 0};
+    const int cand[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 21, 32, 64};
+    int cnt = 0;
+    for (int c : cand) {
+        if (cnt == 4) break;
+        const int th = threads_for(op, nq, c);
+        if (th > kMaxThreads || lds_bytes(op, nq, c, 8) > kMaxLds) continue;
+        const int used = columns(op, nq) * c;
+        if (c == 1 || used * 5 >= th * 4) out[cnt++] = c;
+    }
+    return out;
+}
+
+// One element per workgroup when its columns already fill 80% of the lanes,
+// else the smallest packing that does.
+constexpr int epb_default(int op, int nq)
+{
+    const int cols = columns(op, nq);
+    if (cols * 5 >= round_up_wave(cols) * 4) return 1;
+    const auto ch = epb_choices(op, nq);
+    for (int c : ch)
+        if (c > 1) return c;
+    return 1;
+}
+
+}  // namespace fem

@@ -1,0 +1,193 @@
+"""Python binding of libfem (``include/fem.h``): argument marshalling only.
+
+Every function has the name and argument order of its C entry point.  Array
+arguments may be torch tensors (their ``data_ptr()`` is passed) or raw integer
+addresses; ``stream`` may be a ``torch.cuda.Stream``, a raw ``hipStream_t``
+integer, or None for torch's current stream.  All compute runs in the HIP
+kernels of libfem; there is no fallback: if the library is missing, importing
+:func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from functools import lru_cache
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfem.so")
+
+FEM_OK = 0
+FEM_ERR_ARG = 1
+FEM_ERR_UNSUPPORTED = 2
+FEM_ERR_ALIGN = 3
+FEM_ERR_HIP = 4
+FEM_ERR_NOT_CONVERGED = 5
+FEM_ERR_BREAKDOWN = 6
+FEM_ERR_WORKSPACE = 7
+FEM_ERR_GEOMETRY = 8
+
+FEM_F64, FEM_F32, FEM_BF16, FEM_F16 = 0, 1, 2, 3
+FEM_OP_BP10, FEM_OP_BP35, FEM_OP_BP30 = 0, 1, 2
+FEM_QUAD_GLL, FEM_QUAD_GL = 0, 1
+
+PREC_NAMES = {"f64": FEM_F64, "f32": FEM_F32, "bf16": FEM_BF16, "f16": FEM_F16}
+OP_NAMES = {"BP10": FEM_OP_BP10, "BP35": FEM_OP_BP35, "BP30": FEM_OP_BP30}
+
+
+class FemError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} (status {status})")
+
+
+_vp = C.c_void_p
+_i64 = C.c_int64
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+_SIGS = {
+    "fem_status_str": ([C.c_int], C.c_char_p),
+    "fem_version": ([], C.c_int),
+    "fem_max_degree": ([], C.c_int),
+    "fem_max_elements": ([], _i64),
+    "fem_basis_tables": ([C.c_int] + [_dp] * 7, C.c_int),
+    "fem_geometric_factors": ([C.c_int, _i64, C.c_int, _vp, _vp, _vp, C.c_int, C.c_float, _vp, _vp],
+                              C.c_int),
+    "fem_node_coords": ([C.c_int, _i64, C.c_int, _vp, _vp, _vp], C.c_int),
+    "fem_mass_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_int, C.c_float, _vp],
+                       C.c_int),
+    "fem_stiff_collocated_apply": ([C.c_int, _i64, _vp, _vp, _vp, C.c_double, _vp, _vp, C.c_double,
+                                    C.c_int, C.c_float, _vp], C.c_int),
+    "fem_stiff_dealiased_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp,
+                                   C.c_double, C.c_int, C.c_float, _vp], C.c_int),
+    "fem_stream_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
+    "fem_tune_set": ([C.c_int] * 5, C.c_int),
+    "fem_tune_get": ([C.c_int, C.c_int, C.c_int, _ip, _ip], C.c_int),
+    "fem_kernel_info": ([C.c_int] * 4 + [_ip, _ip], C.c_int),
+    "fem_supported_epb": ([C.c_int] * 3 + [_ip, C.c_int], C.c_int),
+}
+
+
+@lru_cache(maxsize=1)
+def lib() -> C.CDLL:
+    """Load libfem.so (built in-tree by ``__graft_entry__.build()``)."""
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libfem.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+def symbols() -> list[str]:
+    return list(_SIGS)
+
+
+def status_str(status: int) -> str:
+    return lib().fem_status_str(int(status)).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != FEM_OK:
+        raise FemError(status, where)
+
+
+def _ptr(x):
+    """Device/host address of a tensor, or an integer address, or NULL."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x or None
+    return x.data_ptr() or None
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(s, int):
+        return s or None
+    return s.cuda_stream or None
+
+
+# ---------------------------------------------------------------- host entry points
+
+def fem_version() -> int:
+    return lib().fem_version()
+
+
+def fem_max_degree() -> int:
+    return lib().fem_max_degree()
+
+
+def fem_basis_tables(N: int) -> dict:
+    """Quadrature rules and 1-D tables of degree N as host float64 arrays."""
+    nq, ng = N + 1, N + 2
+    out = dict(r_gll=np.zeros(nq), w_gll=np.zeros(nq), r_gl=np.zeros(ng), w_gl=np.zeros(ng),
+               I1d=np.zeros((ng, nq)), D1d=np.zeros((nq, nq)), Dgl=np.zeros((ng, ng)))
+    args = [out[k].ctypes.data_as(_dp) for k in ("r_gll", "w_gll", "r_gl", "w_gl", "I1d", "D1d", "Dgl")]
+    _check(lib().fem_basis_tables(N, *args), "fem_basis_tables")
+    return out
+
+
+def fem_tune_set(op: int, N: int, prec: int, epb: int = 0, grid_cap: int = 0) -> None:
+    _check(lib().fem_tune_set(op, N, prec, epb, grid_cap), "fem_tune_set")
+
+
+def fem_tune_get(op: int, N: int, prec: int) -> tuple[int, int]:
+    e, c = C.c_int(), C.c_int()
+    _check(lib().fem_tune_get(op, N, prec, C.byref(e), C.byref(c)), "fem_tune_get")
+    return e.value, c.value
+
+
+def fem_kernel_info(op: int, N: int, prec: int, epb: int = 0) -> tuple[int, int]:
+    th, lds = C.c_int(), C.c_int()
+    _check(lib().fem_kernel_info(op, N, prec, epb, C.byref(th), C.byref(lds)), "fem_kernel_info")
+    return th.value, lds.value
+
+
+def fem_supported_epb(op: int, N: int, prec: int) -> list[int]:
+    buf = (C.c_int * 8)()
+    n = lib().fem_supported_epb(op, N, prec, buf, 8)
+    if n < 0:
+        raise FemError(-n, "fem_supported_epb")
+    return list(buf[:n])
+
+
+# ---------------------------------------------------------------- device entry points
+
+def fem_geometric_factors(N, E, quad, X, G, wJ, prec=FEM_F64, geo_scale=1.0, bad_count=None,
+                          stream=None) -> None:
+    _check(lib().fem_geometric_factors(N, E, quad, _ptr(X), _ptr(G), _ptr(wJ), prec, geo_scale,
+                                       _ptr(bad_count), _stream(stream)), "fem_geometric_factors")
+
+
+def fem_node_coords(N, E, quad, X, xyz, stream=None) -> None:
+    _check(lib().fem_node_coords(N, E, quad, _ptr(X), _ptr(xyz), _stream(stream)), "fem_node_coords")
+
+
+def fem_mass_apply(N, E, I1d, wJ, u, y, beta=0.0, prec=FEM_F64, geo_scale=1.0, stream=None) -> None:
+    _check(lib().fem_mass_apply(N, E, _ptr(I1d), _ptr(wJ), _ptr(u), _ptr(y), beta, prec, geo_scale,
+                                _stream(stream)), "fem_mass_apply")
+
+
+def fem_stiff_collocated_apply(N, E, D1d, G, wJ, lam, u, y, beta=0.0, prec=FEM_F64, geo_scale=1.0,
+                               stream=None) -> None:
+    _check(lib().fem_stiff_collocated_apply(N, E, _ptr(D1d), _ptr(G), _ptr(wJ), lam, _ptr(u), _ptr(y),
+                                            beta, prec, geo_scale, _stream(stream)),
+           "fem_stiff_collocated_apply")
+
+
+def fem_stiff_dealiased_apply(N, E, I1d, Dgl, G, wJ, lam, u, y, beta=0.0, prec=FEM_F64,
+                              geo_scale=1.0, stream=None) -> None:
+    _check(lib().fem_stiff_dealiased_apply(N, E, _ptr(I1d), _ptr(Dgl), _ptr(G), _ptr(wJ), lam,
+                                           _ptr(u), _ptr(y), beta, prec, geo_scale, _stream(stream)),
+           "fem_stiff_dealiased_apply")
+
+
+def fem_stream_copy(src, dst, nbytes: int, stream=None) -> None:
+    _check(lib().fem_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "fem_stream_copy")

@@ -1,0 +1,110 @@
+"""Device-resident operator data of one hex mesh at degree N.
+
+Plumbing over the C ABI: torch supplies device memory and the stream; the 1-D
+tables come from ``fem_basis_tables`` (host) and the geometric factors from the
+``fem_geometric_factors`` kernel.  Every operator call is one libfem launch.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import fem
+
+TORCH_DTYPE = {fem.FEM_F64: torch.float64, fem.FEM_F32: torch.float32,
+               fem.FEM_BF16: torch.bfloat16, fem.FEM_F16: torch.float16}
+
+
+def out_dtype(prec: int) -> torch.dtype:
+    return torch.float64 if prec == fem.FEM_F64 else torch.float32
+
+
+def default_geo_scale(h: float, kind: str) -> float:
+    """Power-of-two factor that lifts FP16-stored geometric data of a mesh of
+    spacing h into FP16's normal range: metric factors scale like h, scaled
+    Jacobians like h^3 (largest entries about 2^10 h resp. 2^10 h^3 before
+    scaling)."""
+    p = 1 if kind == "G" else 3
+    return float(2.0 ** round(np.log2(2.0 ** 10 / max(h, 1e-30) ** p)))
+
+
+class DeviceMesh:
+    """Element vertices, 1-D tables and lazily built geometric data on one GPU."""
+
+    def __init__(self, N: int, X, device: str | torch.device = "cuda", h: float | None = None):
+        self.N = N
+        self.nq, self.ng = N + 1, N + 2
+        self.np, self.npg = self.nq ** 3, self.ng ** 3
+        self.device = torch.device(device)
+        Xt = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64)) if not torch.is_tensor(X) else X
+        self.X = Xt.to(self.device, torch.float64).contiguous()
+        self.E = int(self.X.shape[0])
+        T = fem.fem_basis_tables(N)
+        self.host_tables = T
+        self.I1d = torch.from_numpy(T["I1d"]).to(self.device)
+        self.D1d = torch.from_numpy(T["D1d"]).to(self.device)
+        self.Dgl = torch.from_numpy(T["Dgl"]).to(self.device)
+        self.h = h if h is not None else 1.0 / max(1.0, round(self.E ** (1.0 / 3.0)))
+        self._geo: dict = {}
+
+    # ---------------------------------------------------------------- geometry
+    def geo_scale(self, prec: int, kind: str = "G") -> float:
+        return default_geo_scale(self.h, kind) if prec == fem.FEM_F16 else 1.0
+
+    def geometry(self, quad: int, prec: int = fem.FEM_F64, want_G: bool = True,
+                 want_wJ: bool = True, kind: str = "G", stream=None):
+        """(G [E,6,npq] or None, wJ [E,npq] or None) in storage precision ``prec``
+        (FP16 data multiplied by ``geo_scale(prec, kind)``)."""
+        key = (quad, prec, want_G, want_wJ, self.geo_scale(prec, kind))
+        if key in self._geo:
+            return self._geo[key]
+        npq = self.np if quad == fem.FEM_QUAD_GLL else self.npg
+        dt = TORCH_DTYPE[prec]
+        G = torch.empty((self.E, 6, npq), dtype=dt, device=self.device) if want_G else None
+        wJ = torch.empty((self.E, npq), dtype=dt, device=self.device) if want_wJ else None
+        bad = torch.zeros(1, dtype=torch.int64, device=self.device)
+        fem.fem_geometric_factors(self.N, self.E, quad, self.X, G, wJ, prec,
+                                  self.geo_scale(prec, kind), bad, stream)
+        nbad = int(bad.item())
+        if nbad:
+            raise fem.FemError(fem.FEM_ERR_GEOMETRY, f"fem_geometric_factors ({nbad} nodes)")
+        self._geo[key] = (G, wJ)
+        return G, wJ
+
+    def drop_geometry(self) -> None:
+        self._geo.clear()
+
+    def node_coords(self, quad: int = fem.FEM_QUAD_GLL, stream=None) -> torch.Tensor:
+        npq = self.np if quad == fem.FEM_QUAD_GLL else self.npg
+        xyz = torch.empty((self.E, npq, 3), dtype=torch.float64, device=self.device)
+        fem.fem_node_coords(self.N, self.E, quad, self.X, xyz, stream)
+        return xyz
+
+    # ---------------------------------------------------------------- operators
+    def _y(self, y, prec):
+        if y is None:
+            return torch.empty((self.E, self.np), dtype=out_dtype(prec), device=self.device)
+        return y
+
+    def mass(self, u, y=None, beta=0.0, prec=fem.FEM_F64, stream=None):
+        _, wJ = self.geometry(fem.FEM_QUAD_GL, prec, want_G=False, kind="wJ")
+        y = self._y(y, prec)
+        fem.fem_mass_apply(self.N, self.E, self.I1d, wJ, u, y, beta, prec,
+                           self.geo_scale(prec, "wJ"), stream)
+        return y
+
+    def stiff35(self, u, y=None, lam=0.0, beta=0.0, prec=fem.FEM_F64, stream=None):
+        G, _ = self.geometry(fem.FEM_QUAD_GLL, prec, want_wJ=False)
+        wJ = self.geometry(fem.FEM_QUAD_GLL, prec, want_G=False)[1] if lam else None
+        y = self._y(y, prec)
+        fem.fem_stiff_collocated_apply(self.N, self.E, self.D1d, G, wJ, lam, u, y, beta, prec,
+                                       self.geo_scale(prec), stream)
+        return y
+
+    def stiff30(self, u, y=None, lam=0.0, beta=0.0, prec=fem.FEM_F64, stream=None):
+        G, _ = self.geometry(fem.FEM_QUAD_GL, prec, want_wJ=False)
+        wJ = self.geometry(fem.FEM_QUAD_GL, prec, want_G=False)[1] if lam else None
+        y = self._y(y, prec)
+        fem.fem_stiff_dealiased_apply(self.N, self.E, self.I1d, self.Dgl, G, wJ, lam, u, y, beta,
+                                      prec, self.geo_scale(prec), stream)
+        return y

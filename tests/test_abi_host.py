@@ -1,0 +1,126 @@
+"""CPU-side checks of libfem: it loads, exports every symbol fem.h declares, and
+its host logic (tables, tune table, argument validation) behaves.  No compute
+call reaches a GPU here: every apply below is rejected during validation,
+before anything is enqueued."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fem():
+    from paper_1711_00903_amd import fem as f
+    if not os.path.exists(f.LIB_PATH):
+        pytest.skip("libfem.so not built")
+    f.lib()
+    return f
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "fem.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fem_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(fem):
+    import ctypes
+    L = ctypes.CDLL(fem.LIB_PATH)
+    syms = header_symbols()
+    assert "fem_stiff_collocated_apply" in syms and len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) <= set(fem.symbols())
+
+
+def test_status_strings(fem):
+    assert fem.status_str(0) == "ok"
+    for s in range(1, 9):
+        assert fem.status_str(s) not in ("ok", "unknown status")
+    assert fem.fem_max_degree() == 15
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_product_tables_match_oracle(fem, N):
+    T = fem.fem_basis_tables(N)
+    O = oracle.tables(N)
+    np.testing.assert_allclose(T["r_gll"], O.rgll, atol=1e-15)
+    np.testing.assert_allclose(T["w_gll"], O.wgll, rtol=1e-13)
+    np.testing.assert_allclose(T["r_gl"], O.rgl, atol=1e-15)
+    np.testing.assert_allclose(T["w_gl"], O.wgl, rtol=1e-13)
+    np.testing.assert_allclose(T["I1d"], O.I, atol=1e-14)
+    np.testing.assert_allclose(T["D1d"], O.D, atol=1e-13 * N * N)
+    np.testing.assert_allclose(T["Dgl"], O.Dgl, atol=1e-13 * N * N)
+
+
+def test_bad_degree(fem):
+    for N in (0, 16, -1):
+        with pytest.raises(fem.FemError):
+            fem.fem_basis_tables(N)
+
+
+def test_tune_table(fem):
+    for op in range(3):
+        for N in range(1, 16):
+            ch = fem.fem_supported_epb(op, N, fem.FEM_F64)
+            assert ch and ch[0] == 1
+            for c in ch:
+                th, lds = fem.fem_kernel_info(op, N, fem.FEM_F64, c)
+                assert th % 64 == 0 and 64 <= th <= 512
+                assert 0 < lds <= 160 * 1024
+    fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 2, 1024)
+    assert fem.fem_tune_get(fem.FEM_OP_BP35, 7, fem.FEM_F64) == (2, 1024)
+    fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 0, 0)
+    assert fem.fem_tune_get(fem.FEM_OP_BP35, 7, fem.FEM_F64)[1] == 0
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 3 * 64 + 1, 0)
+    assert ei.value.status == fem.FEM_ERR_UNSUPPORTED
+    with pytest.raises(fem.FemError):
+        fem.fem_tune_set(5, 7, 0, 0, 0)
+
+
+def test_validation_rejects_before_enqueue(fem):
+    """Each of these fails argument validation; none touches the device."""
+    bad = 0x1000   # a fake, aligned device address: never dereferenced
+    cases = [
+        (lambda: fem.fem_stiff_collocated_apply(0, 4, bad, bad, None, 0.0, bad, bad + 4096, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_collocated_apply(16, 4, bad, bad, None, 0.0, bad, bad + 4096, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_collocated_apply(7, -1, bad, bad, None, 0.0, bad, bad + 4096, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 1.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ARG),   # lambda != 0 needs wJ
+        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad, bad, stream=0),
+         fem.FEM_ERR_ARG),   # u == y
+        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad + 8, 1 << 40, stream=0),
+         fem.FEM_ERR_ALIGN),
+        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad, 1 << 40, prec=7,
+                                                stream=0), fem.FEM_ERR_UNSUPPORTED),
+        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad, 1 << 40, prec=3,
+                                                geo_scale=0.0, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_mass_apply(7, 4, None, bad, bad, 1 << 40, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_mass_apply(3, 1 << 31, bad, bad, bad, 1 << 40, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_dealiased_apply(7, 4, bad, None, bad, None, 0.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_geometric_factors(7, 4, 2, bad, bad, bad, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_geometric_factors(7, 4, 0, bad, None, None, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stream_copy(bad, 1 << 40, 17, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stream_copy(bad, bad + 16, 64, stream=0), fem.FEM_ERR_ARG),
+    ]
+    for i, (f, st) in enumerate(cases):
+        with pytest.raises(fem.FemError) as ei:
+            f()
+        assert ei.value.status == st, (i, ei.value.status, st)
+
+
+def test_empty_calls_are_noops(fem):
+    fem.fem_stiff_collocated_apply(7, 0, None, None, None, 0.0, None, None, stream=0)
+    fem.fem_mass_apply(3, 0, None, None, None, None, stream=0)
+    fem.fem_stiff_dealiased_apply(5, 0, None, None, None, None, 0.0, None, None, stream=0)
+    fem.fem_stream_copy(None, None, 0, stream=0)

@@ -124,3 +124,11 @@ def test_perturbed_grid_keeps_boundary():
     assert np.max(np.abs(d)) <= 0.1 * h + 1e-15
     onb = np.any((np.stack([ix, iy, iz], -1).reshape(-1, 3) % n) == 0, axis=1)
     assert np.all(d[onb] == 0) and np.all(np.abs(d[~onb]).max(axis=1) > 0)
+
+
+def test_chunked_fields_reproduce_single_draw():
+    a = workloads.field(3000, 4)
+    b = np.concatenate([blk for _, blk in workloads.field_chunked(3000, 4, chunk=701)])
+    assert np.array_equal(a, b)
+    rows = np.array([2999, 0, 700, 701, 1500])
+    assert np.array_equal(workloads.field_rows(3000, 4, rows, chunk=250), a[rows])
