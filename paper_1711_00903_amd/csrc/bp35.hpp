@@ -62,7 +62,13 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     constexpr int P = lds_row(NQ, sizeof(TC));
     constexpr int SLAB = NQ * P;
     constexpr int VOL = NQ * SLAB;
-    constexpr bool TREG = NQ <= 10;
+    // Table rows in registers only for small Nq; for larger Nq the LDS copy
+    // leaves the registers to the prefetched geometric factors.
+    constexpr bool TREG = NQ <= 5;
+    // All 6 Nq factors of a column are loaded before the first barrier, so the
+    // element's whole HBM read is in flight at once; beyond Nq = 10 they no
+    // longer fit in registers and each slab's factors are loaded as needed.
+    constexpr bool PREF = NQ <= 10;
 
     __shared__ TC s_D[NQ * NQ];
     __shared__ TC s_u[EPB * VOL];
@@ -99,13 +105,19 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         TC uc[NQ];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
+        const TS *Ge = G + (ok ? e : 0) * (6 * NP) + col;
+        TC gp[PREF ? 6 * NQ : 1];   // gp[f * NQ + k]: factor f at slab k
+        if constexpr (PREF) {
+#pragma unroll
+            for (int x = 0; x < 6 * NQ; ++x)
+                gp[x] = ok ? ld_stream<TC>(Ge, (x / NQ) * NP + (x % NQ) * NC) : TC(0);
+        }
         if (lane) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) su[k * SLAB + me] = uc[k];
         }
         __syncthreads();
 
-        const TS *Ge = G + (ok ? e : 0) * (6 * NP) + col;
         TC wt[NQ];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {
@@ -119,7 +131,14 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
                 qt += uniform_entry(D1d, s_D, k * NQ + m) * uc[m];
             }
             TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
-            if (ok) {
+            if constexpr (PREF) {
+                grr = gp[0 * NQ + k];
+                grs = gp[1 * NQ + k];
+                grt = gp[2 * NQ + k];
+                gss = gp[3 * NQ + k];
+                gst = gp[4 * NQ + k];
+                gtt = gp[5 * NQ + k];
+            } else if (ok) {
                 const int off = k * NC;
                 grr = ld_stream<TC>(Ge, off + 0 * NP);
                 grs = ld_stream<TC>(Ge, off + 1 * NP);
