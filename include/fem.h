@@ -25,10 +25,20 @@
  *  - 1-D tables are FP64, row-major, in device memory: I1d[(N+2)*(N+1)]
  *    (I1d[a][i] = l_i(r~_a)), D1d[(N+1)^2] (D1d[a][i] = l_i'(r_a)),
  *    Dgl[(N+2)^2] (Dgl[a][b] = l~_b'(r~_a)).  fem_basis_tables() fills them.
- *  - Storage precision `prec` applies to u, G and wJ.  y is FP64 when
- *    prec == FEM_F64 and FP32 otherwise; reduced-precision storage computes in
- *    FP32.  FEM_F16 stores G and wJ multiplied by geo_scale (the result is
+ *  - Storage precision `prec` (fem_prec) fixes the types of u, G, wJ and y:
+ *        prec         u          G, wJ      y      arithmetic
+ *        FEM_F64      FP64       FP64       FP64   FP64
+ *        FEM_F32      FP32       FP32       FP32   FP32
+ *        FEM_BF16     BF16       BF16       FP32   FP32
+ *        FEM_F16      FP16       FP16       FP32   FP32
+ *        FEM_BF16G    FP32       BF16       FP32   FP32
+ *        FEM_F16G     FP32       FP16       FP32   FP32
+ *        FEM_F32G64   FP64       FP32       FP64   FP64
+ *        FEM_BF16G64  FP64       BF16       FP64   FP64
+ *        FEM_F16G64   FP64       FP16       FP64   FP64
+ *    The FP16 modes store G and wJ multiplied by geo_scale (> 0; the result is
  *    divided by it), because the raw factors of fine meshes underflow FP16.
+ *    geo_scale is ignored by the other modes.
  *  - Every array argument is a DEVICE pointer owned by the caller, 16-byte
  *    aligned, and must stay valid until the enqueued work has finished.  The
  *    library allocates nothing inside an apply.
@@ -62,7 +72,10 @@ typedef enum {
     FEM_ERR_GEOMETRY = 8       /* a node with non-positive Jacobian         */
 } fem_status;
 
-typedef enum { FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2, FEM_F16 = 3 } fem_prec;
+typedef enum {
+    FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2, FEM_F16 = 3, FEM_BF16G = 4, FEM_F16G = 5,
+    FEM_F32G64 = 6, FEM_BF16G64 = 7, FEM_F16G64 = 8
+} fem_prec;
 typedef enum { FEM_OP_BP10 = 0, FEM_OP_BP35 = 1, FEM_OP_BP30 = 2 } fem_op;
 typedef enum { FEM_QUAD_GLL = 0, FEM_QUAD_GL = 1 } fem_quad;
 
@@ -94,7 +107,8 @@ int fem_basis_tables(int N, double *r_gll, double *w_gll, double *r_gl, double *
  * the N+2 GL points (BP1.0, BP3.0).  Writes, in precision `prec`,
  *   wJ[e][n]    = w_a w_b w_c |J|                    (may be NULL)
  *   G[e][f][n]  = w_a w_b w_c |J| (J^-1 J^-T)_f       (may be NULL)
- * with J = dx/dr; FEM_F16 stores both times geo_scale.  If bad_count is not
+ * with J = dx/dr, in the geometry type of `prec` (see above); the FP16 modes
+ * store both times geo_scale.  If bad_count is not
  * NULL it must point to one device int64 that is incremented once per node
  * with |J| <= 0 (the caller zeroes it). */
 int fem_geometric_factors(int N, int64_t E, int quad, const double *X, void *G, void *wJ,
@@ -128,6 +142,68 @@ int fem_stiff_dealiased_apply(int N, int64_t E, const double *I1d, const double 
  * model section (eq. globalRoof).  src and dst must not overlap; bytes must be
  * a multiple of 16. */
 int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Conjugate gradients on A = S + lambda M, with S the BP3.5 stiffness (GLL
+ * collocation, 6 factors) and M the BP1.0 mass (GL quadrature): symmetric, and
+ * positive definite for lambda > 0 (the screened Poisson operator of the
+ * Problem description section, unassembled, block diagonal).
+ *
+ * mode 0: FP64 CG.  mode 1: mixed precision -- the Krylov iteration runs with
+ * the operator's geometric data stored in `inner_prec`'s geometry type, and
+ * FP32 vectors (FEM_F32, FEM_BF16G, FEM_F16G) or FP64 vectors and arithmetic
+ * (FEM_F32G64, FEM_BF16G64, FEM_F16G64).  Both modes use reliable updates: whenever the
+ * recursive residual has dropped by `delta` (default 0.1) relative to the last
+ * true residual, the iterate is folded into the FP64 x and r = b - A x is
+ * recomputed with the FP64 operator.  The solve stops when the FP64 true
+ * residual satisfies ||b - A x||_2 <= rtol ||b||_2, and reports that value.
+ * The call is blocking: the host reads the residual norm every `check_every`
+ * iterations (default 1).  Dot products are reduced in FP64 in a fixed order,
+ * so a solve is repeatable bit for bit.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int N;
+    int64_t E;
+    const double *I1d, *D1d;   /* device tables (fem_basis_tables)                   */
+    const void *G;             /* FP64 BP3.5 factors at GLL nodes, [E][6][Np]         */
+    const void *wJ;            /* FP64 BP1.0 scaled Jacobians at GL nodes, [E][NpGL]; */
+                               /* NULL iff lambda == 0                                */
+    double lambda;
+    int inner_prec;            /* mode 1: FEM_F32, FEM_BF16G, FEM_F16G, FEM_F32G64,   */
+                               /* FEM_BF16G64 or FEM_F16G64                           */
+    const void *G_lo, *wJ_lo;  /* mode 1: the same data in inner_prec's geometry type */
+    float geo_scale_G;         /* FP16 inner mode: storage scale of G_lo              */
+    float geo_scale_wJ;        /* FP16 inner mode: storage scale of wJ_lo             */
+} fem_cg_operator;
+
+typedef struct {
+    int mode;                  /* 0 = FP64 CG, 1 = mixed precision                    */
+    double rtol;               /* relative FP64 true-residual target                  */
+    int max_iters;             /* iterations of the Krylov loop                       */
+    double delta;              /* reliable-update threshold, (0, 1); 0 = 0.1          */
+    int check_every;           /* host residual check period; 0 = 1                   */
+} fem_cg_options;
+
+typedef struct {
+    int status;                /* FEM_OK, FEM_ERR_NOT_CONVERGED or FEM_ERR_BREAKDOWN  */
+    int iters;                 /* Krylov iterations                                   */
+    int reliable_updates;
+    int hi_matvecs;            /* FP64 operator applications (true residuals)         */
+    double rel_res;            /* final ||b - A x|| / ||b||, evaluated in FP64        */
+    double ms;                 /* wall time of the solve                              */
+} fem_cg_report;
+
+/* Device workspace bytes a solve needs (vectors, partial sums, scalars). */
+size_t fem_cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt);
+
+/* DEVICE, blocking.  Solves A x = b: b and x are FP64 [E][Np] device vectors;
+ * x holds the initial guess on entry and the solution on return.  op, opt and
+ * rep are host structs.  `workspace` is a device buffer of at least
+ * fem_cg_workspace_bytes() bytes (256-byte aligned), owned by the caller.
+ * Returns rep->status, or FEM_ERR_ARG / FEM_ERR_WORKSPACE / FEM_ERR_HIP before
+ * or during the solve. */
+int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
+                 void *workspace, size_t workspace_bytes, fem_cg_report *rep, void *stream);
 
 /* Launch configuration of one (operator, degree, precision): `epb` elements per
  * workgroup (0 = library default) and `grid_cap` workgroups at most (0 = one

@@ -18,12 +18,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfem.so")
 
-SOURCES = [
-    "fem_api.cpp", "basis.cpp", "geometry.hip",
-    "bp35_f64.hip", "bp35_f32.hip", "bp35_bf16.hip", "bp35_f16.hip",
-    "bp10_f64.hip", "bp10_f32.hip", "bp10_bf16.hip", "bp10_f16.hip",
-    "bp30_f64.hip", "bp30_f32.hip", "bp30_bf16.hip", "bp30_f16.hip",
-]
+PRECS = ["f64", "f32", "bf16", "f16", "bf16g", "f16g", "f32g64", "bf16g64", "f16g64"]
+SOURCES = ["fem_api.cpp", "basis.cpp", "geometry.hip", "cg.hip"] + [
+    f"{op}_{p}.hip" for op in ("bp35", "bp10", "bp30") for p in PRECS]
 
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 

@@ -17,15 +17,15 @@
 
 namespace fem {
 
-template <int NQ, int EPB, class TS>
+template <int NQ, int EPB, class TG, class TV>
 __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
     int64_t E, int64_t ngroups, const double *__restrict__ I1d, const double *__restrict__ Dgl,
-    const TS *__restrict__ G, const TS *__restrict__ wJ, typename compute_of<TS>::type lambda,
-    const TS *__restrict__ u, typename output_of<TS>::type *__restrict__ y,
-    typename compute_of<TS>::type beta, typename compute_of<TS>::type oscale)
+    const TG *__restrict__ G, const TG *__restrict__ wJ, typename compute_pair<TG, TV>::type lambda,
+    const TV *__restrict__ u, typename output_of<TV>::type *__restrict__ y,
+    typename compute_pair<TG, TV>::type beta, typename compute_pair<TG, TV>::type oscale)
 {
-    using TC = typename compute_of<TS>::type;
-    using TY = typename output_of<TS>::type;
+    using TC = typename compute_pair<TG, TV>::type;
+    using TY = typename output_of<TV>::type;
     constexpr int NG = NQ + 1;
     constexpr int NP = NQ * NQ * NQ;
     constexpr int NPG = NG * NG * NG;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
         {
             const int64_t nvalid = (E - e0) < EPB ? (E - e0) : EPB;
             const int total = static_cast<int>(nvalid) * NP;
-            const TS *ug = u + e0 * NP;
+            const TV *ug = u + e0 * NP;
             for (int x = t; x < total; x += blockDim.x) {
                 const int s = x / NP, n = x - s * NP;
                 const int k = n / (NQ * NQ), r = n - k * NQ * NQ;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
 
         // gradient on the Gauss grid, metric, weighted gradient (R1 -> R2, R3)
         TC wt[NG];
-        const TS *Ge = G + (ok ? e : 0) * (6 * NPG) + col;
+        const TG *Ge = G + (ok ? e : 0) * (6 * NPG) + col;
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             const TC *row = r1 + c * NG * PG + b * PG;   // q~[c][b][*]
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
         TC V[NQ];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) V[k] = 0;
-        const TS *wJe = wJ + (ok ? e : 0) * NPG + col;
+        const TG *wJe = wJ + (ok ? e : 0) * NPG + col;
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             const TC *rrow = r2 + c * NG * PG + b * PG;   // wr[c][b][*]
@@ -224,55 +224,56 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
     }
 }
 
-template <int NQ, int EPB, class TS>
+template <int NQ, int EPB, class TG, class TV>
 hipError_t bp30_launch_t(const ApplyArgs &a, hipStream_t s)
 {
-    using TC = typename compute_of<TS>::type;
-    using TY = typename output_of<TS>::type;
+    using TC = typename compute_pair<TG, TV>::type;
+    using TY = typename output_of<TV>::type;
     const int64_t ngroups = (a.E + EPB - 1) / EPB;
     int64_t grid = ngroups;
     if (a.grid_cap > 0 && grid > a.grid_cap) grid = a.grid_cap;
     if (grid < 1) return hipSuccess;
-    const TC oscale = (a.prec == P_F16) ? TC(1.0 / a.geo_scale) : TC(1);
-    hipLaunchKernelGGL((bp30_kernel<NQ, EPB, TS>), dim3(static_cast<unsigned>(grid)),
+    const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
+                                                                         : a.out_scale);
+    hipLaunchKernelGGL((bp30_kernel<NQ, EPB, TG, TV>), dim3(static_cast<unsigned>(grid)),
                        dim3(threads_for(2, NQ, EPB)), 0, s, a.E, ngroups, a.I1d, a.Dgl,
-                       static_cast<const TS *>(a.G), static_cast<const TS *>(a.wJ),
-                       static_cast<TC>(a.lambda), static_cast<const TS *>(a.u),
+                       static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
+                       static_cast<TC>(a.lambda), static_cast<const TV *>(a.u),
                        static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale);
     return hipGetLastError();
 }
 
-template <int NQ, class TS>
+template <int NQ, class TG, class TV>
 hipError_t bp30_launch_nq(const ApplyArgs &a, hipStream_t s)
 {
     constexpr auto ch = epb_choices(2, NQ);
     const int epb = a.epb > 0 ? a.epb : epb_default(2, NQ);
-    if (epb == ch[0]) return bp30_launch_t<NQ, ch[0], TS>(a, s);
-    if constexpr (ch[1] > 0) if (epb == ch[1]) return bp30_launch_t<NQ, ch[1], TS>(a, s);
-    if constexpr (ch[2] > 0) if (epb == ch[2]) return bp30_launch_t<NQ, ch[2], TS>(a, s);
-    if constexpr (ch[3] > 0) if (epb == ch[3]) return bp30_launch_t<NQ, ch[3], TS>(a, s);
+    if (epb == ch[0]) return bp30_launch_t<NQ, ch[0], TG, TV>(a, s);
+    if constexpr (ch[1] > 0) if (epb == ch[1]) return bp30_launch_t<NQ, ch[1], TG, TV>(a, s);
+    if constexpr (ch[2] > 0) if (epb == ch[2]) return bp30_launch_t<NQ, ch[2], TG, TV>(a, s);
+    if constexpr (ch[3] > 0) if (epb == ch[3]) return bp30_launch_t<NQ, ch[3], TG, TV>(a, s);
     return hipErrorInvalidConfiguration;
 }
 
-template <class TS>
+template <class TG, class TV>
 hipError_t bp30_launch(const ApplyArgs &a, hipStream_t s)
 {
     switch (a.N + 1) {
-    case 2: return bp30_launch_nq<2, TS>(a, s);
-    case 3: return bp30_launch_nq<3, TS>(a, s);
-    case 4: return bp30_launch_nq<4, TS>(a, s);
-    case 5: return bp30_launch_nq<5, TS>(a, s);
-    case 6: return bp30_launch_nq<6, TS>(a, s);
-    case 7: return bp30_launch_nq<7, TS>(a, s);
-    case 8: return bp30_launch_nq<8, TS>(a, s);
-    case 9: return bp30_launch_nq<9, TS>(a, s);
-    case 10: return bp30_launch_nq<10, TS>(a, s);
-    case 11: return bp30_launch_nq<11, TS>(a, s);
-    case 12: return bp30_launch_nq<12, TS>(a, s);
-    case 13: return bp30_launch_nq<13, TS>(a, s);
-    case 14: return bp30_launch_nq<14, TS>(a, s);
-    case 15: return bp30_launch_nq<15, TS>(a, s);
-    case 16: return bp30_launch_nq<16, TS>(a, s);
+    case 2: return bp30_launch_nq<2, TG, TV>(a, s);
+    case 3: return bp30_launch_nq<3, TG, TV>(a, s);
+    case 4: return bp30_launch_nq<4, TG, TV>(a, s);
+    case 5: return bp30_launch_nq<5, TG, TV>(a, s);
+    case 6: return bp30_launch_nq<6, TG, TV>(a, s);
+    case 7: return bp30_launch_nq<7, TG, TV>(a, s);
+    case 8: return bp30_launch_nq<8, TG, TV>(a, s);
+    case 9: return bp30_launch_nq<9, TG, TV>(a, s);
+    case 10: return bp30_launch_nq<10, TG, TV>(a, s);
+    case 11: return bp30_launch_nq<11, TG, TV>(a, s);
+    case 12: return bp30_launch_nq<12, TG, TV>(a, s);
+    case 13: return bp30_launch_nq<13, TG, TV>(a, s);
+    case 14: return bp30_launch_nq<14, TG, TV>(a, s);
+    case 15: return bp30_launch_nq<15, TG, TV>(a, s);
+    case 16: return bp30_launch_nq<16, TG, TV>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

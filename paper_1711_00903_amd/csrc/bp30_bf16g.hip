@@ -1,0 +1,6 @@
+// BP3.0 kernels: geometric data stored as bf16_t, fields as float.
+#include "bp30.hpp"
+
+namespace fem {
+hipError_t launch_bp30_bf16g(const ApplyArgs &a, hipStream_t s) { return bp30_launch<bf16_t, float>(a, s); }
+}  // namespace fem

@@ -1,0 +1,6 @@
+// BP3.0 kernels: geometric data stored as float, fields as double.
+#include "bp30.hpp"
+
+namespace fem {
+hipError_t launch_bp30_f32g64(const ApplyArgs &a, hipStream_t s) { return bp30_launch<float, double>(a, s); }
+}  // namespace fem

@@ -1,0 +1,6 @@
+// BP3.5 kernels: geometric data stored as f16_t, fields as double.
+#include "bp35.hpp"
+
+namespace fem {
+hipError_t launch_bp35_f16g64(const ApplyArgs &a, hipStream_t s) { return bp35_launch<f16_t, double>(a, s); }
+}  // namespace fem

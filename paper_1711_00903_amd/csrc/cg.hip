@@ -1,0 +1,371 @@
+// cg.hip -- conjugate gradients on the unassembled screened-Poisson operator
+// A = S(BP3.5) + lambda M(BP1.0) (Problem description section: the global
+// operator is block diagonal and symmetric positive definite for lambda > 0).
+//
+// One code path serves both arms:
+//   * FP64 CG: iterates, operator and vectors in FP64;
+//   * mixed precision: the Krylov iteration runs with FP32 vectors and an
+//     operator whose geometric data is stored in FP32, BF16 or FP16;
+// and both use reliable updates (residual replacement, Sleijpen & van der
+// Vorst 1996; the mixed-precision form of Clark et al. 2010): the iterate is
+// accumulated in the iteration precision since the last update, and whenever
+// the recursive residual has dropped by `delta` relative to the last true
+// residual, x += x_lo and r = b - A x are recomputed in FP64.  The solve stops
+// on the FP64 true residual: ||b - A x|| <= rtol ||b||.
+//
+// Dot products accumulate in FP64 with a fixed two-stage reduction (per-block
+// partials, then one block), so a solve is bitwise repeatable.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "fem.h"
+#include "fem_device.hpp"
+#include "launch.hpp"
+
+namespace fem {
+
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+struct CgScalars {
+    double rr;       // r_lo . r_lo of the current iterate
+    double rr_new;   // after the update
+    double pAp;
+    double alpha;
+    double beta;
+    double true_rr;  // ||b - A x||^2 at the last reliable update
+    double bb;       // ||b||^2
+    double pad;
+};
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <class TA, class TB>
+__global__ __launch_bounds__(kRedThreads) void dot_kernel(const TA *__restrict__ a, const TB *__restrict__ b,
+                                                          int64_t n, double *__restrict__ part)
+{
+    __shared__ double sh[kRedThreads];
+    double s = 0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads)
+        s += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Final reduction of kRedBlocks partials into *out, then a scalar step:
+//   what == 0: out = rr (nothing else)
+//   what == 1: pAp: alpha = rr / pAp
+//   what == 2: rr_new: beta = rr_new / rr, rr = rr_new
+enum { FIN_PLAIN = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
+__global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double *__restrict__ part, double *out,
+                                                               CgScalars *sc, int what)
+{
+    __shared__ double sh[kRedThreads];
+    double s = 0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += part[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        *out = s;
+        if (what == FIN_ALPHA) sc->alpha = sc->rr / s;
+        if (what == FIN_BETA) {
+            sc->beta = s / sc->rr;
+            sc->rr = s;
+        }
+    }
+}
+
+// x_lo += alpha p; r_lo -= alpha Ap; partial sums of r_lo . r_lo
+template <class TV>
+__global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl, TV *__restrict__ rl,
+                                                             const TV *__restrict__ p,
+                                                             const TV *__restrict__ Ap, int64_t n,
+                                                             const CgScalars *__restrict__ sc,
+                                                             double *__restrict__ part)
+{
+    __shared__ double sh[kRedThreads];
+    const TV alpha = static_cast<TV>(sc->alpha);
+    double s = 0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+        xl[i] += alpha * p[i];
+        const TV r = rl[i] - alpha * Ap[i];
+        rl[i] = r;
+        s += static_cast<double>(r) * static_cast<double>(r);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = r_lo + beta p
+template <class TV>
+__global__ __launch_bounds__(kRedThreads) void xpay_kernel(TV *__restrict__ p, const TV *__restrict__ rl,
+                                                           int64_t n, const CgScalars *__restrict__ sc)
+{
+    const TV beta = static_cast<TV>(sc->beta);
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads)
+        p[i] = rl[i] + beta * p[i];
+}
+
+// x += x_lo; x_lo = 0
+template <class TV>
+__global__ __launch_bounds__(kRedThreads) void merge_kernel(double *__restrict__ x, TV *__restrict__ xl, int64_t n)
+{
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+        x[i] += static_cast<double>(xl[i]);
+        xl[i] = TV(0);
+    }
+}
+
+// r = b - Ax (FP64); r_lo = (TV) r; optionally p = r_lo; partials of r.r and r_lo.r_lo
+template <class TV>
+__global__ __launch_bounds__(kRedThreads) void residual_kernel(const double *__restrict__ b,
+                                                               const double *__restrict__ Ax,
+                                                               double *__restrict__ r, TV *__restrict__ rl,
+                                                               TV *__restrict__ p, int64_t n,
+                                                               double *__restrict__ part_true,
+                                                               double *__restrict__ part_lo)
+{
+    __shared__ double sh[kRedThreads];
+    double st = 0, sl = 0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+        const double v = b[i] - Ax[i];
+        r[i] = v;
+        const TV w = static_cast<TV>(v);
+        rl[i] = w;
+        if (p) p[i] = w;
+        st += v * v;
+        sl += static_cast<double>(w) * static_cast<double>(w);
+    }
+    st = block_sum(st, sh);
+    if (threadIdx.x == 0) part_true[blockIdx.x] = st;
+    __syncthreads();
+    sl = block_sum(sl, sh);
+    if (threadIdx.x == 0) part_lo[blockIdx.x] = sl;
+}
+
+template <class TV>
+__global__ __launch_bounds__(kRedThreads) void fill_kernel(TV *__restrict__ v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads)
+        v[i] = TV(0);
+}
+
+// ---------------------------------------------------------------------------
+// Host driver.
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+struct Layout {
+    size_t r, tmp, xl, rl, p, Ap, part, sc, total;
+};
+
+Layout layout(int64_t n, size_t vbytes)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.r = take(n * 8);
+    L.tmp = take(n * 8);
+    L.xl = take(n * vbytes);
+    L.rl = take(n * vbytes);
+    L.p = take(n * vbytes);
+    L.Ap = take(n * vbytes);
+    L.part = take(3 * kRedBlocks * sizeof(double));
+    L.sc = take(sizeof(CgScalars));
+    L.total = off;
+    return L;
+}
+
+bool check(hipError_t e) { return e == hipSuccess; }
+
+struct Ctx {
+    const fem_cg_operator *op;
+    hipStream_t s;
+    int64_t n;
+    unsigned grid;
+};
+
+// y = A u with operator data in precision `prec` (FP64 vectors for FEM_F64,
+// FP32 otherwise).
+hipError_t apply_A(const Ctx &c, int prec, const void *u, void *y)
+{
+    const fem_cg_operator *op = c.op;
+    const bool hi = prec == FEM_F64;   // the FP64 operator of the true residuals
+    ApplyArgs a{};
+    a.N = op->N;
+    a.E = op->E;
+    a.I1d = op->I1d;
+    a.D1d = op->D1d;
+    a.u = u;
+    a.y = y;
+    a.prec = prec;
+    // stiffness: y = S u
+    a.op = OP_BP35;
+    a.G = hi ? op->G : op->G_lo;
+    a.wJ = nullptr;
+    a.lambda = 0.0;
+    a.beta = 0.0;
+    a.geo_scale = op->geo_scale_G;
+    fem_tune_get(OP_BP35, a.N, prec, &a.epb, &a.grid_cap);
+    hipError_t e = launch_bp35(a, c.s);
+    if (e != hipSuccess || op->lambda == 0.0) return e;
+    // mass: y += lambda M u
+    a.op = OP_BP10;
+    a.G = nullptr;
+    a.wJ = hi ? op->wJ : op->wJ_lo;
+    a.beta = 1.0;
+    a.out_scale = op->lambda;
+    a.geo_scale = op->geo_scale_wJ;
+    fem_tune_get(OP_BP10, a.N, prec, &a.epb, &a.grid_cap);
+    return launch_bp10(a, c.s);
+}
+
+template <class TV>
+int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, const double *b, double *x,
+            void *ws, fem_cg_report *rep, hipStream_t s)
+{
+    const int64_t np = static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
+    const int64_t n = op->E * np;
+    const Layout L = layout(n, sizeof(TV));
+    char *w = static_cast<char *>(ws);
+    double *r = reinterpret_cast<double *>(w + L.r);
+    double *tmp = reinterpret_cast<double *>(w + L.tmp);
+    TV *xl = reinterpret_cast<TV *>(w + L.xl);
+    TV *rl = reinterpret_cast<TV *>(w + L.rl);
+    TV *p = reinterpret_cast<TV *>(w + L.p);
+    TV *Ap = reinterpret_cast<TV *>(w + L.Ap);
+    double *part = reinterpret_cast<double *>(w + L.part);
+    double *part2 = part + kRedBlocks;
+    double *part3 = part + 2 * kRedBlocks;
+    CgScalars *sc = reinterpret_cast<CgScalars *>(w + L.sc);
+    Ctx c{op, s, n, kRedBlocks};
+    const dim3 G(kRedBlocks), B(kRedThreads);
+    const auto t0 = std::chrono::steady_clock::now();
+    CgScalars h{};
+    auto fetch = [&]() -> bool {
+        if (!check(hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s))) return false;
+        return check(hipStreamSynchronize(s));
+    };
+    auto fin = [&](const double *pp, double *out, int what) {
+        hipLaunchKernelGGL(finalize_kernel, dim3(1), B, 0, s, pp, out, sc, what);
+    };
+    // true residual r = b - A x; r_lo = (TV) r.  At the start (set_p) also
+    // p = r_lo and rr = r_lo.r_lo; at a reliable update the replaced r_lo.r_lo
+    // goes to rr_new and its partials stay in part2, where the beta step below
+    // reads them (beta = replaced rr / previous rr).
+    auto true_residual = [&](bool set_p) -> hipError_t {
+        hipError_t e = apply_A(c, FEM_F64, x, tmp);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(residual_kernel<TV>, G, B, 0, s, b, tmp, r, rl, set_p ? p : nullptr, n, part,
+                           part2);
+        fin(part, &sc->true_rr, FIN_PLAIN);
+        fin(part2, set_p ? &sc->rr : &sc->rr_new, FIN_PLAIN);
+        return hipGetLastError();
+    };
+
+    rep->iters = 0;
+    rep->reliable_updates = 0;
+    rep->hi_matvecs = 0;
+    rep->status = FEM_OK;
+    if (!check(hipMemsetAsync(sc, 0, sizeof(CgScalars), s))) return FEM_ERR_HIP;
+    hipLaunchKernelGGL((dot_kernel<double, double>), G, B, 0, s, b, b, n, part3);
+    fin(part3, &sc->bb, FIN_PLAIN);
+    hipLaunchKernelGGL(fill_kernel<TV>, G, B, 0, s, xl, n);
+    if (true_residual(true) != hipSuccess) return FEM_ERR_HIP;
+    rep->hi_matvecs = 1;
+    if (!fetch()) return FEM_ERR_HIP;
+    const double bnorm = std::sqrt(h.bb);
+    const double target = opt->rtol * bnorm;
+    double rmax = std::sqrt(h.true_rr);
+    double rel = bnorm > 0 ? rmax / bnorm : 0.0;
+    const double delta = opt->delta > 0 ? opt->delta : 0.1;
+    const int every = opt->check_every > 0 ? opt->check_every : 1;
+    bool converged = rmax <= target || bnorm == 0.0;
+    int it = 0;
+    while (!converged && it < opt->max_iters) {
+        ++it;
+        if (apply_A(c, prec_lo, p, Ap) != hipSuccess) return FEM_ERR_HIP;
+        hipLaunchKernelGGL((dot_kernel<TV, TV>), G, B, 0, s, p, Ap, n, part);
+        fin(part, &sc->pAp, FIN_ALPHA);
+        hipLaunchKernelGGL(update_kernel<TV>, G, B, 0, s, xl, rl, p, Ap, n, sc, part2);
+        fin(part2, &sc->rr_new, FIN_PLAIN);
+        if (it % every == 0 || it == opt->max_iters) {
+            if (!fetch()) return FEM_ERR_HIP;
+            if (!(h.pAp > 0.0) || !std::isfinite(h.rr_new)) {
+                rep->status = FEM_ERR_BREAKDOWN;
+                break;
+            }
+            const double rn = std::sqrt(h.rr_new);
+            if (rn < delta * rmax || rn <= target) {
+                // reliable update: fold the low-precision iterate into x and
+                // replace the recursive residual by the true one
+                hipLaunchKernelGGL(merge_kernel<TV>, G, B, 0, s, x, xl, n);
+                if (true_residual(false) != hipSuccess) return FEM_ERR_HIP;
+                rep->reliable_updates += 1;
+                rep->hi_matvecs += 1;
+                if (!fetch()) return FEM_ERR_HIP;
+                rmax = std::sqrt(h.true_rr);
+                rel = rmax / bnorm;
+                if (rmax <= target) {
+                    converged = true;
+                    break;
+                }
+            }
+        }
+        // beta = rr_new / rr; rr = rr_new; p = r_lo + beta p
+        fin(part2, &sc->rr_new, FIN_BETA);
+        hipLaunchKernelGGL(xpay_kernel<TV>, G, B, 0, s, p, rl, n, sc);
+        if (hipGetLastError() != hipSuccess) return FEM_ERR_HIP;
+    }
+    if (!converged) {
+        // fold in the last low-precision iterate and report the true residual
+        hipLaunchKernelGGL(merge_kernel<TV>, G, B, 0, s, x, xl, n);
+        if (true_residual(false) != hipSuccess) return FEM_ERR_HIP;
+        rep->hi_matvecs += 1;
+        if (!fetch()) return FEM_ERR_HIP;
+        rel = std::sqrt(h.true_rr) / bnorm;
+        converged = std::sqrt(h.true_rr) <= target;
+    }
+    if (!check(hipStreamSynchronize(s))) return FEM_ERR_HIP;
+    const auto t1 = std::chrono::steady_clock::now();
+    rep->iters = it;
+    rep->rel_res = rel;
+    rep->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (rep->status == FEM_OK && !converged) rep->status = FEM_ERR_NOT_CONVERGED;
+    return rep->status;
+}
+
+}  // namespace
+
+size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt)
+{
+    const int64_t np = static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
+    return layout(op->E * np, (opt->mode == 0 || f64_fields(op->inner_prec)) ? 8 : 4).total;
+}
+
+int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,
+             fem_cg_report *rep, hipStream_t s)
+{
+    if (opt->mode == 0) return solve_t<double>(op, opt, FEM_F64, b, x, ws, rep, s);
+    if (f64_fields(op->inner_prec)) return solve_t<double>(op, opt, op->inner_prec, b, x, ws, rep, s);
+    return solve_t<float>(op, opt, op->inner_prec, b, x, ws, rep, s);
+}
+
+}  // namespace fem

@@ -16,14 +16,29 @@ hipError_t launch_bp35_f64(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp35_f32(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp35_bf16(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp35_f16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_bf16g(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_f16g(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_f32g64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_bf16g64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp35_f16g64(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp10_f64(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp10_f32(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp10_bf16(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp10_f16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_bf16g(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_f16g(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_f32g64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_bf16g64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp10_f16g64(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp30_f64(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp30_f32(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp30_bf16(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp30_f16(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_bf16g(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_f16g(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_f32g64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_bf16g64(const ApplyArgs &, hipStream_t);
+hipError_t launch_bp30_f16g64(const ApplyArgs &, hipStream_t);
 
 hipError_t launch_bp35(const ApplyArgs &a, hipStream_t s)
 {
@@ -32,6 +47,11 @@ hipError_t launch_bp35(const ApplyArgs &a, hipStream_t s)
     case P_F32: return launch_bp35_f32(a, s);
     case P_BF16: return launch_bp35_bf16(a, s);
     case P_F16: return launch_bp35_f16(a, s);
+    case P_BF16G: return launch_bp35_bf16g(a, s);
+    case P_F16G: return launch_bp35_f16g(a, s);
+    case P_F32G64: return launch_bp35_f32g64(a, s);
+    case P_BF16G64: return launch_bp35_bf16g64(a, s);
+    case P_F16G64: return launch_bp35_f16g64(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -42,6 +62,11 @@ hipError_t launch_bp10(const ApplyArgs &a, hipStream_t s)
     case P_F32: return launch_bp10_f32(a, s);
     case P_BF16: return launch_bp10_bf16(a, s);
     case P_F16: return launch_bp10_f16(a, s);
+    case P_BF16G: return launch_bp10_bf16g(a, s);
+    case P_F16G: return launch_bp10_f16g(a, s);
+    case P_F32G64: return launch_bp10_f32g64(a, s);
+    case P_BF16G64: return launch_bp10_bf16g64(a, s);
+    case P_F16G64: return launch_bp10_f16g64(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -52,6 +77,11 @@ hipError_t launch_bp30(const ApplyArgs &a, hipStream_t s)
     case P_F32: return launch_bp30_f32(a, s);
     case P_BF16: return launch_bp30_bf16(a, s);
     case P_F16: return launch_bp30_f16(a, s);
+    case P_BF16G: return launch_bp30_bf16g(a, s);
+    case P_F16G: return launch_bp30_f16g(a, s);
+    case P_F32G64: return launch_bp30_f32g64(a, s);
+    case P_BF16G64: return launch_bp30_bf16g64(a, s);
+    case P_F16G64: return launch_bp30_f16g64(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -94,15 +124,19 @@ bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
     bool found = false;
     for (int c = 0; c < n; ++c) found |= (ch[c] == epb);
     if (!found) return false;
-    const int bytes = prec == P_F64 ? 8 : 4;
+    const int bytes = f64_fields(prec) ? 8 : 4;   // compute type held in LDS
     info->threads = threads_for(op, N + 1, epb);
     info->lds_bytes = lds_bytes(op, N + 1, epb, bytes);
     return true;
 }
 
+size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt);
+int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,
+             fem_cg_report *rep, hipStream_t s);
+
 // Process-wide launch configuration: (op, N, prec) -> (epb, grid_cap).
-static std::atomic<int> g_epb[3][kMaxN + 1][4];
-static std::atomic<int> g_cap[3][kMaxN + 1][4];
+static std::atomic<int> g_epb[3][kMaxN + 1][P_COUNT];
+static std::atomic<int> g_cap[3][kMaxN + 1][P_COUNT];
 
 }  // namespace fem
 
@@ -114,14 +148,10 @@ constexpr int64_t kMaxElements = 2147483647LL;
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-size_t prec_bytes(int prec)
-{
-    switch (prec) {
-    case FEM_F64: return 8;
-    case FEM_F32: return 4;
-    default: return 2;
-    }
-}
+// Bytes per value of the field vectors u and y, and of the geometric data.
+size_t field_bytes(int prec) { return f64_fields(prec) ? 8 : (prec == FEM_BF16 || prec == FEM_F16) ? 2 : 4; }
+size_t out_bytes(int prec) { return f64_fields(prec) ? 8 : 4; }
+bool is_f16(int prec) { return is_f16_prec(prec); }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb)
 {
@@ -133,14 +163,13 @@ int common_checks(int op, int N, int64_t E, int prec, float geo_scale, const voi
 {
     if (N < 1 || N > kMaxN) return FEM_ERR_ARG;
     if (E < 0 || E > kMaxElements) return FEM_ERR_ARG;
-    if (prec < FEM_F64 || prec > FEM_F16) return FEM_ERR_UNSUPPORTED;
-    if (prec == FEM_F16 && !(geo_scale > 0.0f)) return FEM_ERR_ARG;
+    if (prec < 0 || prec >= P_COUNT) return FEM_ERR_UNSUPPORTED;
+    if (is_f16(prec) && !(geo_scale > 0.0f)) return FEM_ERR_ARG;
     if (E == 0) return FEM_OK;
     if (!u || !y) return FEM_ERR_ARG;
     if (!aligned16(u) || !aligned16(y)) return FEM_ERR_ALIGN;
     const int64_t np = static_cast<int64_t>(N + 1) * (N + 1) * (N + 1);
-    const size_t ybytes = prec == FEM_F64 ? 8 : 4;
-    if (overlap(u, E * np * prec_bytes(prec), y, E * np * ybytes)) return FEM_ERR_ARG;
+    if (overlap(u, E * np * field_bytes(prec), y, E * np * out_bytes(prec))) return FEM_ERR_ARG;
     (void)op;
     return FEM_OK;
 }
@@ -206,8 +235,8 @@ int fem_geometric_factors(int N, int64_t E, int quad, const double *X, void *G, 
 {
     if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
     if (quad != FEM_QUAD_GLL && quad != FEM_QUAD_GL) return FEM_ERR_ARG;
-    if (prec < FEM_F64 || prec > FEM_F16) return FEM_ERR_UNSUPPORTED;
-    if (prec == FEM_F16 && !(geo_scale > 0.0f)) return FEM_ERR_ARG;
+    if (prec < 0 || prec >= P_COUNT) return FEM_ERR_UNSUPPORTED;
+    if (is_f16(prec) && !(geo_scale > 0.0f)) return FEM_ERR_ARG;
     if (E == 0) return FEM_OK;
     if (!X || (!G && !wJ)) return FEM_ERR_ARG;
     if (!aligned16(X) || (G && !aligned16(G)) || (wJ && !aligned16(wJ))) return FEM_ERR_ALIGN;
@@ -283,9 +312,57 @@ int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
     return finish(launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
 }
 
+static int cg_check(const fem_cg_operator *op, const fem_cg_options *opt)
+{
+    if (!op || !opt) return FEM_ERR_ARG;
+    if (op->N < 1 || op->N > kMaxN || op->E < 0 || op->E > kMaxElements) return FEM_ERR_ARG;
+    if (opt->mode != 0 && opt->mode != 1) return FEM_ERR_ARG;
+    if (!(opt->rtol > 0.0) || opt->max_iters < 0 || opt->delta < 0.0 || opt->delta >= 1.0 ||
+        opt->check_every < 0)
+        return FEM_ERR_ARG;
+    if (op->lambda < 0.0) return FEM_ERR_ARG;
+    if (op->E == 0) return FEM_OK;
+    if (!op->I1d || !op->D1d || !op->G || (op->lambda != 0.0 && !op->wJ)) return FEM_ERR_ARG;
+    if (!aligned16(op->G) || (op->wJ && !aligned16(op->wJ)) || !aligned16(op->I1d) || !aligned16(op->D1d))
+        return FEM_ERR_ALIGN;
+    if (opt->mode == 1) {
+        const int p = op->inner_prec;
+        if (p != FEM_F32 && p != FEM_BF16G && p != FEM_F16G && p != FEM_F32G64 && p != FEM_BF16G64 &&
+            p != FEM_F16G64)
+            return FEM_ERR_UNSUPPORTED;
+        if (!op->G_lo || (op->lambda != 0.0 && !op->wJ_lo)) return FEM_ERR_ARG;
+        if (!aligned16(op->G_lo) || (op->wJ_lo && !aligned16(op->wJ_lo))) return FEM_ERR_ALIGN;
+        if (is_f16(p) && !(op->geo_scale_G > 0.0f && (op->lambda == 0.0 || op->geo_scale_wJ > 0.0f)))
+            return FEM_ERR_ARG;
+    }
+    return FEM_OK;
+}
+
+size_t fem_cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt)
+{
+    if (cg_check(op, opt) != FEM_OK) return 0;
+    return cg_workspace_bytes(op, opt);
+}
+
+int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
+                 void *workspace, size_t workspace_bytes, fem_cg_report *rep, void *stream)
+{
+    int st = cg_check(op, opt);
+    if (st != FEM_OK) return st;
+    if (!rep) return FEM_ERR_ARG;
+    *rep = fem_cg_report{};
+    if (op->E == 0) return FEM_OK;
+    if (!b || !x || !workspace) return FEM_ERR_ARG;
+    if (!aligned16(b) || !aligned16(x) || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return FEM_ERR_ALIGN;
+    const int64_t n = op->E * static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
+    if (overlap(b, n * 8, x, n * 8)) return FEM_ERR_ARG;
+    if (workspace_bytes < cg_workspace_bytes(op, opt)) return FEM_ERR_WORKSPACE;
+    return cg_solve(op, opt, b, x, workspace, rep, static_cast<hipStream_t>(stream));
+}
+
 int fem_tune_set(int op, int N, int prec, int epb, int grid_cap)
 {
-    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3 || epb < 0 || grid_cap < 0)
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec >= P_COUNT || epb < 0 || grid_cap < 0)
         return FEM_ERR_ARG;
     if (epb != 0) {
         KernelInfo ki;
@@ -298,14 +375,14 @@ int fem_tune_set(int op, int N, int prec, int epb, int grid_cap)
 
 int fem_tune_get(int op, int N, int prec, int *epb, int *grid_cap)
 {
-    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3 || !epb || !grid_cap)
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec >= P_COUNT || !epb || !grid_cap)
         return FEM_ERR_ARG;
     return tune_lookup(op, N, prec, epb, grid_cap);
 }
 
 int fem_kernel_info(int op, int N, int prec, int epb, int *threads, int *lds_bytes_out)
 {
-    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3) return FEM_ERR_ARG;
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec >= P_COUNT) return FEM_ERR_ARG;
     KernelInfo ki;
     if (!kernel_info(op, N, prec, epb, &ki)) return FEM_ERR_UNSUPPORTED;
     if (threads) *threads = ki.threads;
@@ -315,7 +392,7 @@ int fem_kernel_info(int op, int N, int prec, int epb, int *threads, int *lds_byt
 
 int fem_supported_epb(int op, int N, int prec, int *epbs, int cap)
 {
-    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec > 3 || cap < 0)
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec >= P_COUNT || cap < 0)
         return -FEM_ERR_ARG;
     return supported_epb(op, N, prec, epbs, cap);
 }

@@ -16,8 +16,14 @@ namespace fem {
 struct bf16_t { uint16_t bits; };
 using f16_t = _Float16;
 
-template <class T> struct compute_of { using type = float; };
-template <> struct compute_of<double> { using type = double; };
+// Arithmetic type of a kernel with geometric data TG and fields TV: FP64 as
+// soon as the fields are FP64 (rounding the fields to FP32 would swamp the
+// smallest modes of ill-conditioned operators), FP32 otherwise.
+template <class TG, class TV> struct compute_pair {
+    using type = typename std::conditional<std::is_same<TG, double>::value ||
+                                               std::is_same<TV, double>::value,
+                                           double, float>::type;
+};
 
 template <class T> struct output_of { using type = float; };
 template <> struct output_of<double> { using type = double; };
@@ -29,6 +35,9 @@ __device__ __forceinline__ float to_compute(bf16_t v, float)
     return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
 }
 __device__ __forceinline__ float to_compute(f16_t v, float) { return static_cast<float>(v); }
+__device__ __forceinline__ double to_compute(float v, double) { return v; }
+__device__ __forceinline__ double to_compute(bf16_t v, double) { return to_compute(v, 0.0f); }
+__device__ __forceinline__ double to_compute(f16_t v, double) { return static_cast<float>(v); }
 
 template <class TC, class TS>
 __device__ __forceinline__ TC ld(const TS *__restrict__ p, int64_t idx)
@@ -52,16 +61,18 @@ template <> __device__ __forceinline__ f16_t from_double<f16_t>(double v) { retu
 
 // Non-temporal load for data that is streamed exactly once (geometric factors):
 // keeps them from evicting the field vectors from the caches.
+__device__ __forceinline__ double nt_load(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float nt_load(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16_t nt_load(const bf16_t *p)
+{
+    return bf16_t{__builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p))};
+}
+__device__ __forceinline__ f16_t nt_load(const f16_t *p) { return __builtin_nontemporal_load(p); }
+
 template <class TC, class TS>
 __device__ __forceinline__ TC ld_stream(const TS *__restrict__ p, int64_t idx)
 {
-    return to_compute(__builtin_nontemporal_load(p + idx), TC{});
-}
-template <>
-__device__ __forceinline__ float ld_stream<float, bf16_t>(const bf16_t *__restrict__ p, int64_t idx)
-{
-    const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
-    return __uint_as_float(static_cast<uint32_t>(__builtin_nontemporal_load(q + idx)) << 16);
+    return to_compute(nt_load(p + idx), TC{});
 }
 
 // ---------------------------------------------------------------------------

@@ -131,7 +131,7 @@ hipError_t launch_geometry(int N, int64_t E, int quad, const double *X, void *G,
     const int64_t total = E * nq * nq * nq;
     if (total == 0) return hipSuccess;
     const NodeRule rule = make_rule(N, quad);
-    const double scale = prec == P_F16 ? static_cast<double>(geo_scale) : 1.0;
+    const double scale = is_f16_prec(prec) ? static_cast<double>(geo_scale) : 1.0;
     const unsigned grid = grid_for(total, 256);
     switch (prec) {
     case P_F64:
@@ -139,14 +139,19 @@ hipError_t launch_geometry(int N, int64_t E, int quad, const double *X, void *G,
                            static_cast<double *>(G), static_cast<double *>(wJ), scale, bad);
         break;
     case P_F32:
+    case P_F32G64:
         hipLaunchKernelGGL(geometry_kernel<float>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
                            static_cast<float *>(G), static_cast<float *>(wJ), scale, bad);
         break;
     case P_BF16:
+    case P_BF16G:
+    case P_BF16G64:
         hipLaunchKernelGGL(geometry_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
                            static_cast<bf16_t *>(G), static_cast<bf16_t *>(wJ), scale, bad);
         break;
     case P_F16:
+    case P_F16G:
+    case P_F16G64:
         hipLaunchKernelGGL(geometry_kernel<f16_t>, dim3(grid), dim3(256), 0, s, nq, E, X, rule,
                            static_cast<f16_t *>(G), static_cast<f16_t *>(wJ), scale, bad);
         break;

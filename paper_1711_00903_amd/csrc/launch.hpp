@@ -7,7 +7,13 @@
 
 namespace fem {
 
-enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
+enum Prec {
+    P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3, P_BF16G = 4, P_F16G = 5,
+    P_F32G64 = 6, P_BF16G64 = 7, P_F16G64 = 8, P_COUNT = 9
+};
+constexpr bool is_f16_prec(int p) { return p == P_F16 || p == P_F16G || p == P_F16G64; }
+// FP64 fields (and FP64 arithmetic) in these modes
+constexpr bool f64_fields(int p) { return p == P_F64 || p == P_F32G64 || p == P_BF16G64 || p == P_F16G64; }
 enum Op { OP_BP10 = 0, OP_BP35 = 1, OP_BP30 = 2 };
 
 constexpr int kMaxN = 15;
@@ -26,6 +32,7 @@ struct ApplyArgs {
     void *y;             // [E][Np]
     double lambda;
     double beta;
+    double out_scale = 1.0;   // y = out_scale * (A u) + beta y (FP16 modes also divide by geo_scale)
     float geo_scale;
     int prec;
     int epb;             // elements per workgroup, 0 = default

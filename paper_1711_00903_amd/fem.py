@@ -28,11 +28,14 @@ FEM_ERR_BREAKDOWN = 6
 FEM_ERR_WORKSPACE = 7
 FEM_ERR_GEOMETRY = 8
 
-FEM_F64, FEM_F32, FEM_BF16, FEM_F16 = 0, 1, 2, 3
+FEM_F64, FEM_F32, FEM_BF16, FEM_F16, FEM_BF16G, FEM_F16G = 0, 1, 2, 3, 4, 5
+FEM_F32G64, FEM_BF16G64, FEM_F16G64 = 6, 7, 8
 FEM_OP_BP10, FEM_OP_BP35, FEM_OP_BP30 = 0, 1, 2
 FEM_QUAD_GLL, FEM_QUAD_GL = 0, 1
 
-PREC_NAMES = {"f64": FEM_F64, "f32": FEM_F32, "bf16": FEM_BF16, "f16": FEM_F16}
+PREC_NAMES = {"f64": FEM_F64, "f32": FEM_F32, "bf16": FEM_BF16, "f16": FEM_F16,
+              "bf16g": FEM_BF16G, "f16g": FEM_F16G, "f32g64": FEM_F32G64,
+              "bf16g64": FEM_BF16G64, "f16g64": FEM_F16G64}
 OP_NAMES = {"BP10": FEM_OP_BP10, "BP35": FEM_OP_BP35, "BP30": FEM_OP_BP30}
 
 
@@ -46,6 +49,26 @@ _vp = C.c_void_p
 _i64 = C.c_int64
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
+
+class CgOperator(C.Structure):
+    _fields_ = [("N", C.c_int), ("E", C.c_int64), ("I1d", C.c_void_p), ("D1d", C.c_void_p),
+                ("G", C.c_void_p), ("wJ", C.c_void_p), ("lam", C.c_double), ("inner_prec", C.c_int),
+                ("G_lo", C.c_void_p), ("wJ_lo", C.c_void_p), ("geo_scale_G", C.c_float),
+                ("geo_scale_wJ", C.c_float)]
+
+
+class CgOptions(C.Structure):
+    _fields_ = [("mode", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int),
+                ("delta", C.c_double), ("check_every", C.c_int)]
+
+
+class CgReport(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("reliable_updates", C.c_int),
+                ("hi_matvecs", C.c_int), ("rel_res", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
 
 _SIGS = {
     "fem_status_str": ([C.c_int], C.c_char_p),
@@ -63,6 +86,9 @@ _SIGS = {
     "fem_stiff_dealiased_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp,
                                    C.c_double, C.c_int, C.c_float, _vp], C.c_int),
     "fem_stream_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
+    "fem_cg_workspace_bytes": ([C.POINTER(CgOperator), C.POINTER(CgOptions)], C.c_size_t),
+    "fem_cg_solve": ([C.POINTER(CgOperator), C.POINTER(CgOptions), _vp, _vp, _vp, C.c_size_t,
+                      C.POINTER(CgReport), _vp], C.c_int),
     "fem_tune_set": ([C.c_int] * 5, C.c_int),
     "fem_tune_get": ([C.c_int, C.c_int, C.c_int, _ip, _ip], C.c_int),
     "fem_kernel_info": ([C.c_int] * 4 + [_ip, _ip], C.c_int),
@@ -191,3 +217,20 @@ def fem_stiff_dealiased_apply(N, E, I1d, Dgl, G, wJ, lam, u, y, beta=0.0, prec=F
 
 def fem_stream_copy(src, dst, nbytes: int, stream=None) -> None:
     _check(lib().fem_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "fem_stream_copy")
+
+
+def fem_cg_workspace_bytes(op: CgOperator, opt: CgOptions) -> int:
+    return int(lib().fem_cg_workspace_bytes(C.byref(op), C.byref(opt)))
+
+
+def fem_cg_solve(op: CgOperator, opt: CgOptions, b, x, workspace, workspace_bytes: int,
+                 stream=None, raise_on_error: bool = True) -> CgReport:
+    """Blocking CG solve; returns the report.  FEM_ERR_NOT_CONVERGED and
+    FEM_ERR_BREAKDOWN are returned in the report (not raised) unless
+    raise_on_error and the status is an argument / runtime error."""
+    rep = CgReport()
+    st = lib().fem_cg_solve(C.byref(op), C.byref(opt), _ptr(b), _ptr(x), _ptr(workspace),
+                            workspace_bytes, C.byref(rep), _stream(stream))
+    if raise_on_error and st not in (FEM_OK, FEM_ERR_NOT_CONVERGED, FEM_ERR_BREAKDOWN):
+        raise FemError(st, "fem_cg_solve")
+    return rep

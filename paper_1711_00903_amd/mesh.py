@@ -11,12 +11,26 @@ import torch
 
 from . import fem
 
-TORCH_DTYPE = {fem.FEM_F64: torch.float64, fem.FEM_F32: torch.float32,
-               fem.FEM_BF16: torch.bfloat16, fem.FEM_F16: torch.float16}
+# storage dtype of the geometric data (G, wJ) and of the field vectors (u) per precision mode
+GEO_DTYPE = {fem.FEM_F64: torch.float64, fem.FEM_F32: torch.float32,
+             fem.FEM_BF16: torch.bfloat16, fem.FEM_F16: torch.float16,
+             fem.FEM_BF16G: torch.bfloat16, fem.FEM_F16G: torch.float16,
+             fem.FEM_F32G64: torch.float32, fem.FEM_BF16G64: torch.bfloat16,
+             fem.FEM_F16G64: torch.float16}
+FIELD_DTYPE = {fem.FEM_F64: torch.float64, fem.FEM_F32: torch.float32,
+               fem.FEM_BF16: torch.bfloat16, fem.FEM_F16: torch.float16,
+               fem.FEM_BF16G: torch.float32, fem.FEM_F16G: torch.float32,
+               fem.FEM_F32G64: torch.float64, fem.FEM_BF16G64: torch.float64,
+               fem.FEM_F16G64: torch.float64}
+TORCH_DTYPE = FIELD_DTYPE
 
 
 def out_dtype(prec: int) -> torch.dtype:
-    return torch.float64 if prec == fem.FEM_F64 else torch.float32
+    return torch.float64 if FIELD_DTYPE[prec] == torch.float64 else torch.float32
+
+
+def is_f16(prec: int) -> bool:
+    return prec in (fem.FEM_F16, fem.FEM_F16G, fem.FEM_F16G64)
 
 
 def default_geo_scale(h: float, kind: str) -> float:
@@ -49,7 +63,7 @@ class DeviceMesh:
 
     # ---------------------------------------------------------------- geometry
     def geo_scale(self, prec: int, kind: str = "G") -> float:
-        return default_geo_scale(self.h, kind) if prec == fem.FEM_F16 else 1.0
+        return default_geo_scale(self.h, kind) if is_f16(prec) else 1.0
 
     def geometry(self, quad: int, prec: int = fem.FEM_F64, want_G: bool = True,
                  want_wJ: bool = True, kind: str = "G", stream=None):
@@ -59,7 +73,7 @@ class DeviceMesh:
         if key in self._geo:
             return self._geo[key]
         npq = self.np if quad == fem.FEM_QUAD_GLL else self.npg
-        dt = TORCH_DTYPE[prec]
+        dt = GEO_DTYPE[prec]
         G = torch.empty((self.E, 6, npq), dtype=dt, device=self.device) if want_G else None
         wJ = torch.empty((self.E, npq), dtype=dt, device=self.device) if want_wJ else None
         bad = torch.zeros(1, dtype=torch.int64, device=self.device)
@@ -108,3 +122,28 @@ class DeviceMesh:
         fem.fem_stiff_dealiased_apply(self.N, self.E, self.I1d, self.Dgl, G, wJ, lam, u, y, beta,
                                       prec, self.geo_scale(prec), stream)
         return y
+
+    # ---------------------------------------------------------------- CG
+    def cg_solve(self, b, x, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
+                 rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
+                 check_every: int = 1, stream=None) -> dict:
+        """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors."""
+        G64, _ = self.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
+        _, wJ64 = self.geometry(fem.FEM_QUAD_GL, fem.FEM_F64, want_G=False, kind="wJ")
+        op = fem.CgOperator(N=self.N, E=self.E, I1d=self.I1d.data_ptr(), D1d=self.D1d.data_ptr(),
+                            G=G64.data_ptr(), wJ=wJ64.data_ptr() if lam else None, lam=lam,
+                            inner_prec=inner_prec)
+        if mode == 1:
+            Glo, _ = self.geometry(fem.FEM_QUAD_GLL, inner_prec, want_wJ=False)
+            _, wJlo = self.geometry(fem.FEM_QUAD_GL, inner_prec, want_G=False, kind="wJ")
+            op.G_lo = Glo.data_ptr()
+            op.wJ_lo = wJlo.data_ptr() if lam else None
+            op.geo_scale_G = self.geo_scale(inner_prec, "G")
+            op.geo_scale_wJ = self.geo_scale(inner_prec, "wJ")
+        opt = fem.CgOptions(mode=mode, rtol=rtol, max_iters=max_iters, delta=delta,
+                            check_every=check_every)
+        nbytes = fem.fem_cg_workspace_bytes(op, opt)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        rep = fem.fem_cg_solve(op, opt, b, x, ws, nbytes, stream)
+        del ws
+        return rep.as_dict()

@@ -100,7 +100,7 @@ def test_validation_rejects_before_enqueue(fem):
          fem.FEM_ERR_ARG),   # u == y
         (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad + 8, 1 << 40, stream=0),
          fem.FEM_ERR_ALIGN),
-        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad, 1 << 40, prec=7,
+        (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad, 1 << 40, prec=12,
                                                 stream=0), fem.FEM_ERR_UNSUPPORTED),
         (lambda: fem.fem_stiff_collocated_apply(7, 4, bad, bad, None, 0.0, bad, 1 << 40, prec=3,
                                                 geo_scale=0.0, stream=0), fem.FEM_ERR_ARG),
@@ -124,3 +124,33 @@ def test_empty_calls_are_noops(fem):
     fem.fem_mass_apply(3, 0, None, None, None, None, stream=0)
     fem.fem_stiff_dealiased_apply(5, 0, None, None, None, None, 0.0, None, None, stream=0)
     fem.fem_stream_copy(None, None, 0, stream=0)
+
+
+def test_cg_struct_layout_matches_header(fem, tmp_path):
+    """The ctypes structs of the binding have the header's field offsets."""
+    import ctypes
+    import subprocess
+    fields = {"fem_cg_operator": ("CgOperator", ["N", "E", "I1d", "D1d", "G", "wJ", "lambda", "inner_prec",
+                                                 "G_lo", "wJ_lo", "geo_scale_G", "geo_scale_wJ"]),
+              "fem_cg_options": ("CgOptions", ["mode", "rtol", "max_iters", "delta", "check_every"]),
+              "fem_cg_report": ("CgReport", ["status", "iters", "reliable_updates", "hi_matvecs",
+                                             "rel_res", "ms"])}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "fem.h"', 'int main(void) {']
+    for cs, (_, names) in fields.items():
+        src.append(f'printf("%zu\\n", sizeof({cs}));')
+        for nm in names:
+            src.append(f'printf("%zu\\n", offsetof({cs}, {nm}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    k = 0
+    for cs, (py, names) in fields.items():
+        S = getattr(fem, py)
+        assert ctypes.sizeof(S) == vals[k], cs
+        k += 1
+        for (pyname, _), nm in zip(S._fields_, names):
+            assert getattr(S, pyname).offset == vals[k], (cs, nm)
+            k += 1

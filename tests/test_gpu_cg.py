@@ -1,0 +1,126 @@
+"""GPU conjugate gradients (fem_cg_solve) against the oracle.
+
+The system is the CG workload's operator A = S(BP3.5) + 1.0 M(BP1.0) at N = 7
+on the first 512 elements of the 64^3 mesh (h = 1/64, same conditioning as
+the full workload), right-hand side sin(pi x) sin(pi y) sin(pi z) + 1e-3 noise
+at every local GLL node.  Both sides build b from their own node coordinates.
+A GPU solution is accepted when the oracle's own FP64 evaluation of
+||b - A x|| / ||b|| meets the requested tolerance (within 10%): several
+solutions are correct, so the residual, not x, is compared.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.cg import cg, true_relative_residual
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 7
+NGRID = 64
+E = 512
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_00903_amd import fem
+    from paper_1711_00903_amd.mesh import DeviceMesh
+    fem.lib()
+    X = workloads.element_vertices(NGRID, E=E)
+    noise = workloads.rhs_noise(E, N + 1)
+    dev = DeviceMesh(N, X, h=1.0 / NGRID)
+    xyz = dev.node_coords()
+    bt = (torch.sin(math.pi * xyz[..., 0]) * torch.sin(math.pi * xyz[..., 1]) *
+          torch.sin(math.pi * xyz[..., 2]) + 1e-3 * torch.from_numpy(noise).cuda()).contiguous()
+    pb = oracle.Problem(N, X)
+    xo = oracle.node_coords(N, X, "gll")
+    bo = np.sin(np.pi * xo[..., 0]) * np.sin(np.pi * xo[..., 1]) * np.sin(np.pi * xo[..., 2]) + 1e-3 * noise
+    A = lambda v: pb.cg_operator(v, 1.0)
+    return fem, dev, bt, bo, A
+
+
+def solve(setup, mode, inner, rtol, **kw):
+    fem, dev, bt, bo, A = setup
+    x = torch.zeros_like(bt)
+    rep = dev.cg_solve(bt, x, lam=1.0, mode=mode, inner_prec=inner, rtol=rtol, **kw)
+    torch.cuda.synchronize()
+    return rep, x
+
+
+def test_rhs_agrees(setup):
+    fem, dev, bt, bo, A = setup
+    np.testing.assert_allclose(bt.cpu().numpy(), bo, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("mode,inner", [(0, 0), (1, 6), (1, 7), (1, 8)])
+def test_cg_converges_oracle_residual(setup, mode, inner):
+    fem, dev, bt, bo, A = setup
+    rtol = 1e-8
+    rep, x = solve(setup, mode, inner, rtol)
+    print(f"mode={mode} inner={inner}: {rep}")
+    assert rep["status"] == fem.FEM_OK, rep
+    assert rep["rel_res"] <= rtol
+    res = true_relative_residual(A, bo, x.cpu().numpy())
+    assert res <= 1.1 * rtol, res
+
+
+def test_fp64_iterations_match_oracle_cg(setup):
+    """Same recurrences in exact arithmetic: the GPU FP64 CG needs about as many
+    iterations as the oracle's textbook CG for the same tolerance."""
+    fem, dev, bt, bo, A = setup
+    rtol = 1e-6
+    rep, x = solve(setup, 0, 0, rtol)
+    _, it, _ = cg(A, bo, rtol=rtol)
+    assert abs(rep["iters"] - it) <= max(3, 0.1 * it), (rep["iters"], it)
+
+
+def test_fp32_vectors_report_truthfully(setup):
+    """With FP32 Krylov vectors the iteration stalls on this operator (its
+    condition number times FP32 roundoff is about 0.5); the solver must then
+    stop at max_iters and report the true FP64 residual of the x it returns."""
+    fem, dev, bt, bo, A = setup
+    rep, x = solve(setup, 1, 1, 1e-8, max_iters=3000)
+    res = true_relative_residual(A, bo, x.cpu().numpy())
+    assert rep["status"] in (fem.FEM_OK, fem.FEM_ERR_NOT_CONVERGED)
+    assert abs(rep["rel_res"] - res) <= 1e-3 * res + 1e-12
+
+
+def test_repeatable_bitwise(setup):
+    r1, x1 = solve(setup, 1, 7, 1e-7)
+    r2, x2 = solve(setup, 1, 7, 1e-7)
+    assert r1["iters"] == r2["iters"] and torch.equal(x1, x2)
+
+
+def test_not_converged_and_initial_guess(setup):
+    fem, dev, bt, bo, A = setup
+    rep, x = solve(setup, 0, 0, 1e-10, max_iters=5)
+    assert rep["status"] == fem.FEM_ERR_NOT_CONVERGED and rep["iters"] == 5
+    # restart from the returned iterate: the solve continues and converges
+    rep2 = dev.cg_solve(bt, x, lam=1.0, mode=0, rtol=1e-7)
+    torch.cuda.synchronize()
+    assert rep2["status"] == fem.FEM_OK
+    assert true_relative_residual(A, bo, x.cpu().numpy()) <= 1.1e-7
+
+
+def test_bad_arguments(setup):
+    fem, dev, bt, bo, A = setup
+    G64, _ = dev.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
+    op = fem.CgOperator(N=N, E=E, I1d=dev.I1d.data_ptr(), D1d=dev.D1d.data_ptr(), G=G64.data_ptr(),
+                        wJ=None, lam=1.0, inner_prec=1)
+    opt = fem.CgOptions(mode=0, rtol=1e-8, max_iters=10, delta=0.1, check_every=1)
+    assert fem.fem_cg_workspace_bytes(op, opt) == 0          # lambda != 0 needs wJ
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_cg_solve(op, opt, bt, bt.clone(), None, 0)
+    assert ei.value.status == fem.FEM_ERR_ARG
+    op.lam = 0.0
+    nb = fem.fem_cg_workspace_bytes(op, opt)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_cg_solve(op, opt, bt, bt.clone(), ws, nb - 256)
+    assert ei.value.status == fem.FEM_ERR_WORKSPACE
