@@ -116,6 +116,92 @@ def cpu_baseline(X, u, budget_s: float) -> dict:
                       f"{len(times)} passes, median pass {t * 1e3:.1f} ms"}
 
 
+CG_ARMS = [("fp64", 0, 0), ("f32g64", 1, 6), ("bf16g64", 1, 7), ("f16g64", 1, 8), ("f32", 1, 1)]
+
+
+def run_cg(args) -> int:
+    """Time to solution of (S + M) x = b, N = 7, 64^3 elements (134M local DOFs):
+    FP64 CG against mixed precision (reduced-precision geometric data), all with
+    FP64 reliable updates and the same stopping rule on the FP64 true residual."""
+    import math
+
+    import torch
+
+    import workloads
+    from paper_1711_00903_amd import fem
+    from paper_1711_00903_amd.mesh import DeviceMesh
+
+    fem.lib()
+    n = args.cg_grid
+    Ncg = 7
+    X = workloads.element_vertices(n)
+    E = X.shape[0]
+    log(f"cg: N={Ncg} E={E}: building inputs")
+    dev = DeviceMesh(Ncg, X, h=1.0 / n)
+    xyz = dev.node_coords()
+    b = torch.sin(math.pi * xyz[..., 0]) * torch.sin(math.pi * xyz[..., 1]) * torch.sin(math.pi * xyz[..., 2])
+    del xyz
+    noise = torch.empty_like(b)
+    for start, blk in workloads.field_chunked(E, Ncg + 1, seed=workloads.SEED_RHS_NOISE, chunk=1 << 15):
+        noise[start:start + blk.shape[0]] = torch.from_numpy(blk).cuda()
+    b = (b + 1e-3 * noise).contiguous()
+    del noise
+    arms = [a for a in CG_ARMS if a[0] in args.cg_arms.split(",")]
+    for _, mode, prec in arms:   # build all geometric data before any timing
+        dev.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
+        dev.geometry(fem.FEM_QUAD_GL, fem.FEM_F64, want_G=False, kind="wJ")
+        if mode == 1:
+            dev.geometry(fem.FEM_QUAD_GLL, prec, want_wJ=False)
+            dev.geometry(fem.FEM_QUAD_GL, prec, want_G=False, kind="wJ")
+    torch.cuda.synchronize()
+    out = {"workload": f"cg_n7_e{E}", "E": E, "N": Ncg, "dofs": E * (Ncg + 1) ** 3, "lambda": 1.0,
+           "fused": not args.cg_unfused, "arms": {}}
+    tau = args.cg_rtol
+    if args.cg_floor_iters > 0:
+        # attainable FP64 accuracy: run FP64 CG far past convergence and take the
+        # median true residual over the second half of its reliable updates
+        x = torch.zeros_like(b)
+        rep = dev.cg_solve(b, x, lam=1.0, mode=0, rtol=1e-16, max_iters=args.cg_floor_iters,
+                           unfused=args.cg_unfused, history=4096)
+        hist = rep.pop("history")
+        tail = sorted(hist[len(hist) // 2:])
+        floor = tail[len(tail) // 2]
+        out["floor"] = {"median_rel_res": floor, "min_rel_res": min(hist), "updates": len(hist),
+                        "iters": rep["iters"], "ms": rep["ms"]}
+        log(f"cg: floor run {rep}; median of last half {floor:.3e}")
+        tau = max(args.cg_rtol, 2.0 * floor)
+        del x
+    out["tau"] = tau
+    for name, mode, prec in arms:
+        x = torch.zeros_like(b)
+        maxit = args.cg_max_iters if name != "f32" else min(args.cg_max_iters, 4000)
+        rep = dev.cg_solve(b, x, lam=1.0, mode=mode, inner_prec=prec, rtol=tau, max_iters=maxit,
+                           unfused=args.cg_unfused)
+        log(f"cg: {name}: {rep}")
+        rec = dict(rep)
+        if args.cg_oracle:
+            import oracle
+            from oracle.cg import true_relative_residual
+            oracle.set_threads(0)
+            pb = oracle.Problem(Ncg, X)
+            xo = oracle.node_coords(Ncg, X, "gll")
+            bo = (np.sin(np.pi * xo[..., 0]) * np.sin(np.pi * xo[..., 1]) * np.sin(np.pi * xo[..., 2])
+                  + 1e-3 * workloads.rhs_noise(E, Ncg + 1))
+            del xo
+            rec["oracle_rel_res"] = true_relative_residual(lambda v: pb.cg_operator(v, 1.0), bo,
+                                                           x.cpu().numpy())
+            log(f"cg: {name}: oracle residual {rec['oracle_rel_res']:.3e}")
+        out["arms"][name] = rec
+        del x
+        torch.cuda.empty_cache()
+    fp = out["arms"].get("fp64")
+    for name, rec in out["arms"].items():
+        if fp and rec["status"] == 0 and fp["status"] == 0:
+            rec["speedup_vs_fp64"] = fp["ms"] / rec["ms"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,7 +211,22 @@ def main() -> int:
                     help="seconds of CPU-oracle timing (0 disables the CPU leg)")
     ap.add_argument("--epb", type=int, default=0, help="elements per workgroup (0 = library default)")
     ap.add_argument("--grid-cap", type=int, default=0, help="workgroups at most (0 = uncapped)")
+    ap.add_argument("--cg", action="store_true", help="time the CG workload instead")
+    ap.add_argument("--cg-grid", type=int, default=64)
+    ap.add_argument("--cg-rtol", type=float, default=1e-10)
+    ap.add_argument("--cg-floor-iters", type=int, default=0,
+                    help="first run FP64 CG this long and set the tolerance to max(rtol, 2 x floor)")
+    ap.add_argument("--cg-max-iters", type=int, default=20000)
+    ap.add_argument("--cg-arms", default="fp64,f32g64,bf16g64,f16g64,f32")
+    ap.add_argument("--cg-oracle", action="store_true", help="oracle re-evaluates each final residual")
+    ap.add_argument("--cg-unfused", action="store_true",
+                    help="separate stiffness / mass / dot / direction kernels in the CG iteration")
     args = ap.parse_args()
+    if args.cg:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            return 2
+        return run_cg(args)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -21,7 +21,13 @@
  *    each already multiplied by the quadrature weights and |J| (the diagonal
  *    blocks of the matrix G^e, eq. Gdef); Npq = Np for BP3.5 (GLL nodes) and
  *    NpGL for BP3.0 (GL nodes).  Scaled Jacobians wJ are [E][Npq] (the
- *    diagonal of J^e).
+ *    diagonal of J^e).  Inside one element's factor block (n points per
+ *    direction), node (i,j,k) sits at ((k / W) n^2 + i + n j) W + k % W:
+ *    the k-values of each (i,j) column are interleaved in groups of W so that
+ *    one thread loads W of them with a single 16-byte (or narrower) load.
+ *    W = fem_geo_vector_width(N, quad, prec) depends on n and the storage type
+ *    (W = 1 is the plain i-fastest order).  fem_geometric_factors() writes
+ *    this layout.
  *  - 1-D tables are FP64, row-major, in device memory: I1d[(N+2)*(N+1)]
  *    (I1d[a][i] = l_i(r~_a)), D1d[(N+1)^2] (D1d[a][i] = l_i'(r_a)),
  *    Dgl[(N+2)^2] (Dgl[a][b] = l~_b'(r~_a)).  fem_basis_tables() fills them.
@@ -114,6 +120,10 @@ int fem_basis_tables(int N, double *r_gll, double *w_gll, double *r_gl, double *
 int fem_geometric_factors(int N, int64_t E, int quad, const double *X, void *G, void *wJ,
                           int prec, float geo_scale, int64_t *bad_count, void *stream);
 
+/* Interleave width W of the geometric-data layout (see the conventions above)
+ * for degree N, quadrature `quad` and precision `prec`; 0 on bad arguments. */
+int fem_geo_vector_width(int N, int quad, int prec);
+
 /* DEVICE.  Physical coordinates xyz[e][n][0..2] (FP64) of the element's tensor
  * nodes (quad as above) under the trilinear map of X. */
 int fem_node_coords(int N, int64_t E, int quad, const double *X, double *xyz, void *stream);
@@ -182,6 +192,12 @@ typedef struct {
     int max_iters;             /* iterations of the Krylov loop                       */
     double delta;              /* reliable-update threshold, (0, 1); 0 = 0.1          */
     int check_every;           /* host residual check period; 0 = 1                   */
+    int unfused;               /* 1: separate stiffness, mass, dot and direction      */
+                               /* kernels; 0: the one-pass operator kernel (FP64      */
+                               /* vectors) that also updates p and forms p . Ap       */
+    double *history;           /* HOST array or NULL: the true relative residual at   */
+                               /* the start and after each reliable update           */
+    int history_len;           /* capacity of history                                 */
 } fem_cg_options;
 
 typedef struct {
@@ -189,6 +205,7 @@ typedef struct {
     int iters;                 /* Krylov iterations                                   */
     int reliable_updates;
     int hi_matvecs;            /* FP64 operator applications (true residuals)         */
+    int history_count;         /* entries written to opt->history                     */
     double rel_res;            /* final ||b - A x|| / ||b||, evaluated in FP64        */
     double ms;                 /* wall time of the solve                              */
 } fem_cg_report;

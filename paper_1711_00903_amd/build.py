@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfem.so")
 
 PRECS = ["f64", "f32", "bf16", "f16", "bf16g", "f16g", "f32g64", "bf16g64", "f16g64"]
-SOURCES = ["fem_api.cpp", "basis.cpp", "geometry.hip", "cg.hip"] + [
+SOURCES = ["fem_api.cpp", "basis.cpp", "geometry.hip", "cg.hip",
+           "cgop_f64.hip", "cgop_f32g64.hip", "cgop_bf16g64.hip", "cgop_f16g64.hip"] + [
     f"{op}_{p}.hip" for op in ("bp35", "bp10", "bp30") for p in PRECS]
 
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
@@ -39,9 +40,18 @@ def hipcc() -> str:
     return h
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _newest_header() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hs.append(os.path.join(INCLUDE, "fem.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(path), _newest_header()):
+        return obj
     cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
@@ -53,12 +63,13 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every source for gfx950 and link ``libfem.so``; returns its path."""
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every source for gfx950 and link ``libfem.so``; returns its path.
+    With ``incremental``, objects newer than their source and every header are kept."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
@@ -71,4 +82,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -36,6 +36,7 @@ __global__ __launch_bounds__(threads_for(0, NQ, EPB)) void bp10_kernel(
     constexpr int SB = NQ * NG * PG;   // V[k][b][a]
     constexpr int SLOT = SU + SA + SB;
     constexpr bool TREG = NQ <= 8;
+    constexpr int W = geo_vec(NG, sizeof(TG));   // Gauss slabs per vector load of wJ
 
     __shared__ TC s_I[NG * NQ];
     __shared__ TC s_w[EPB * SLOT];
@@ -70,18 +71,28 @@ __global__ __launch_bounds__(threads_for(0, NQ, EPB)) void bp10_kernel(
         const int64_t e0 = g * EPB;
         // stage u of the group's elements (contiguous in global memory)
         {
-            const int64_t nvalid = (E - e0) < EPB ? (E - e0) : EPB;
-            const int total = static_cast<int>(nvalid) * NP;
-            const TV *ug = u + e0 * NP;
-            for (int x = t; x < total; x += blockDim.x) {
-                const int s = x / NP, n = x - s * NP;
-                const int k = n / (NQ * NQ), r = n - k * NQ * NQ;
-                const int jj = r / NQ, ii = r - jj * NQ;
-                s_w[s * SLOT + k * NQ * PQ + jj * PQ + ii] = ld<TC>(ug, x);
-            }
+            const int nvalid = static_cast<int>((E - e0) < EPB ? (E - e0) : EPB);
+            stage_fields<NQ, EPB, threads_for(0, NQ, EPB), SLOT, PQ>(s_w, u + e0 * NP, nvalid);
         }
         const int64_t e = e0 + slot;
         const bool ok = lane && e < E;
+        // The element's scaled Jacobians (this Gauss column) and, with beta, the
+        // old output are requested now, so their latency overlaps the
+        // interpolation phases.
+        TC wj[NG];
+        if (ok) {
+            const TG *wJe = wJ + e * NPG + col * W;
+#pragma unroll
+            for (int cq = 0; cq < NG / W; ++cq) ld_stream_vec<W>(wJe + cq * NCG * W, wj + cq * W);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NG; ++c) wj[c] = TC(0);
+        }
+        TC yold[NQ];
+        if (beta != TC(0) && ph4 && ok) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) yold[k] = static_cast<TC>(y[e * NP + j4 * NQ + i4 + k * NQ * NQ]);
+        }
         __syncthreads();
 
         // r-interpolation: T[k][j][a] = sum_i I[a][i] u[k][j][i]
@@ -111,13 +122,12 @@ __global__ __launch_bounds__(threads_for(0, NQ, EPB)) void bp10_kernel(
             }
 #pragma unroll
             for (int k = 0; k < NQ; ++k) V[k] = 0;
-            const TG *wJe = wJ + (ok ? e : 0) * NPG + col;
 #pragma unroll
             for (int c = 0; c < NG; ++c) {
                 TC q = 0;
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) q += uniform_entry(I1d, s_I, c * NQ + k) * T2[k];
-                const TC wq = ok ? q * ld_stream<TC>(wJe, c * NCG) : TC(0);
+                const TC wq = q * wj[c];
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) V[k] += uniform_entry(I1d, s_I, c * NQ + k) * wq;
             }
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(threads_for(0, NQ, EPB)) void bp10_kernel(
                 for (int m = 0; m < NG; ++m) s += Ici[m] * row[m];
                 s *= oscale;
                 const int64_t idx = base + k * NQ * NQ;
-                if (beta != TC(0)) s += beta * static_cast<TC>(y[idx]);
+                if (beta != TC(0)) s += beta * yold[k];
                 y[idx] = static_cast<TY>(s);
             }
         }

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
     constexpr int R3 = NG * NG * PG;
     constexpr int SLOT = R1 + R2 + R3;
     constexpr bool TREG = NQ <= 6;
+    constexpr int W = geo_vec(NG, sizeof(TG));   // Gauss slabs per vector load of G / wJ
 
     __shared__ TC s_I[NG * NQ];
     __shared__ TC s_D[NG * NG];
@@ -78,15 +79,8 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t e0 = g * EPB;
         {
-            const int64_t nvalid = (E - e0) < EPB ? (E - e0) : EPB;
-            const int total = static_cast<int>(nvalid) * NP;
-            const TV *ug = u + e0 * NP;
-            for (int x = t; x < total; x += blockDim.x) {
-                const int s = x / NP, n = x - s * NP;
-                const int k = n / (NQ * NQ), r = n - k * NQ * NQ;
-                const int jj = r / NQ, ii = r - jj * NQ;
-                s_w[s * SLOT + k * NQ * PQ + jj * PQ + ii] = ld<TC>(ug, x);
-            }
+            const int nvalid = static_cast<int>((E - e0) < EPB ? (E - e0) : EPB);
+            stage_fields<NQ, EPB, threads_for(2, NQ, EPB), SLOT, PQ>(s_w, u + e0 * NP, nvalid);
         }
         const int64_t e = e0 + slot;
         const bool ok = lane && e < E;
@@ -133,7 +127,8 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
 
         // gradient on the Gauss grid, metric, weighted gradient (R1 -> R2, R3)
         TC wt[NG];
-        const TG *Ge = G + (ok ? e : 0) * (6 * NPG) + col;
+        TC gw[6 * W];   // the six factors of W Gauss slabs
+        const TG *Ge = G + (ok ? e : 0) * (6 * NPG) + col * W;
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             const TC *row = r1 + c * NG * PG + b * PG;   // q~[c][b][*]
@@ -147,13 +142,16 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
             }
             TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
             if (ok) {
-                const int off = c * NCG;
-                grr = ld_stream<TC>(Ge, off + 0 * NPG);
-                grs = ld_stream<TC>(Ge, off + 1 * NPG);
-                grt = ld_stream<TC>(Ge, off + 2 * NPG);
-                gss = ld_stream<TC>(Ge, off + 3 * NPG);
-                gst = ld_stream<TC>(Ge, off + 4 * NPG);
-                gtt = ld_stream<TC>(Ge, off + 5 * NPG);
+                if (c % W == 0) {
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) ld_stream_vec<W>(Ge + f * NPG + (c / W) * NCG * W, gw + f * W);
+                }
+                grr = gw[0 * W + c % W];
+                grs = gw[1 * W + c % W];
+                grt = gw[2 * W + c % W];
+                gss = gw[3 * W + c % W];
+                gst = gw[4 * W + c % W];
+                gtt = gw[5 * W + c % W];
             }
             if (lane) {
                 r2[c * NG * PG + meg] = grr * qr + grs * qs + grt * qt;
@@ -167,7 +165,8 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
         TC V[NQ];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) V[k] = 0;
-        const TG *wJe = wJ + (ok ? e : 0) * NPG + col;
+        const TG *wJe = wJ + (ok ? e : 0) * NPG + col * W;
+        TC wjv[W];
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             const TC *rrow = r2 + c * NG * PG + b * PG;   // wr[c][b][*]
@@ -179,7 +178,10 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
                 s += DbT[m] * scol[m * PG];
                 s += uniform_entry(Dgl, s_D, m * NG + c) * wt[m];
             }
-            if (lambda != TC(0) && ok) s += lambda * ld<TC>(wJe, c * NCG) * qg[c];
+            if (lambda != TC(0) && ok) {
+                if (c % W == 0) ld_stream_vec<W>(wJe + (c / W) * NCG * W, wjv);
+                s += lambda * wjv[c % W] * qg[c];
+            }
 #pragma unroll
             for (int k = 0; k < NQ; ++k) V[k] += uniform_entry(I1d, s_I, c * NQ + k) * s;
         }

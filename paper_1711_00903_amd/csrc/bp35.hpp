@@ -48,6 +48,34 @@ __device__ __forceinline__ TC uniform_entry(const double *__restrict__ g, const 
     else return s[idx];
 }
 
+// Stage the fields of a group of `nvalid` consecutive elements (contiguous in
+// global memory) into LDS as [slot][k][j][i] with row length PQ.  Every thread
+// issues all of its loads before its first LDS store, so the group's loads are
+// in flight together instead of one round trip per loop iteration.
+template <int NQ, int EPB, int NT, int SLOT, int PQ, class TC, class TV>
+__device__ __forceinline__ void stage_fields(TC *__restrict__ s_w, const TV *__restrict__ ug, int nvalid)
+{
+    constexpr int NP = NQ * NQ * NQ;
+    constexpr int NS = (EPB * NP + NT - 1) / NT;
+    const int total = nvalid * NP;
+    TC v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int x = static_cast<int>(threadIdx.x) + s * NT;
+        v[s] = x < total ? ld<TC>(ug, x) : TC(0);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int x = static_cast<int>(threadIdx.x) + s * NT;
+        if (x < total) {
+            const int sl = x / NP, n = x - sl * NP;
+            const int k = n / (NQ * NQ), r = n - k * NQ * NQ;
+            const int jj = r / NQ, ii = r - jj * NQ;
+            s_w[sl * SLOT + k * NQ * PQ + jj * PQ + ii] = v[s];
+        }
+    }
+}
+
 template <int NQ, int EPB, class TG, class TV>
 __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     int64_t E, int64_t ngroups, const double *__restrict__ D1d, const TG *__restrict__ G,
@@ -69,6 +97,7 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     // element's whole HBM read is in flight at once; beyond Nq = 10 they no
     // longer fit in registers and each slab's factors are loaded as needed.
     constexpr bool PREF = NQ <= 10;
+    constexpr int W = geo_vec(NQ, sizeof(TG));   // slabs per vector load of geometric data
 
     __shared__ TC s_D[NQ * NQ];
     __shared__ TC s_u[EPB * VOL];
@@ -105,13 +134,21 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         TC uc[NQ];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
-        const TG *Ge = G + (ok ? e : 0) * (6 * NP) + col;
+        const TG *Ge = G + (ok ? e : 0) * (6 * NP) + col * W;
         TC gp[PREF ? 6 * NQ : 1];   // gp[f * NQ + k]: factor f at slab k
         if constexpr (PREF) {
+            if (ok) {
 #pragma unroll
-            for (int x = 0; x < 6 * NQ; ++x)
-                gp[x] = ok ? ld_stream<TC>(Ge, (x / NQ) * NP + (x % NQ) * NC) : TC(0);
+                for (int f = 0; f < 6; ++f)
+#pragma unroll
+                    for (int kq = 0; kq < NQ / W; ++kq)
+                        ld_stream_vec<W>(Ge + f * NP + kq * NC * W, gp + f * NQ + kq * W);
+            } else {
+#pragma unroll
+                for (int x = 0; x < 6 * NQ; ++x) gp[x] = TC(0);
+            }
         }
+        TC gw[PREF ? 1 : 6 * W];    // non-prefetched: the factors of W slabs at a time
         if (lane) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) su[k * SLAB + me] = uc[k];
@@ -139,13 +176,16 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
                 gst = gp[4 * NQ + k];
                 gtt = gp[5 * NQ + k];
             } else if (ok) {
-                const int off = k * NC;
-                grr = ld_stream<TC>(Ge, off + 0 * NP);
-                grs = ld_stream<TC>(Ge, off + 1 * NP);
-                grt = ld_stream<TC>(Ge, off + 2 * NP);
-                gss = ld_stream<TC>(Ge, off + 3 * NP);
-                gst = ld_stream<TC>(Ge, off + 4 * NP);
-                gtt = ld_stream<TC>(Ge, off + 5 * NP);
+                if (k % W == 0) {
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) ld_stream_vec<W>(Ge + f * NP + (k / W) * NC * W, gw + f * W);
+                }
+                grr = gw[0 * W + k % W];
+                grs = gw[1 * W + k % W];
+                grt = gw[2 * W + k % W];
+                gss = gw[3 * W + k % W];
+                gst = gw[4 * W + k % W];
+                gtt = gw[5 * W + k % W];
             }
             const TC wr = grr * qr + grs * qs + grt * qt;
             const TC ws = grs * qr + gss * qs + gst * qt;
@@ -170,7 +210,8 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             }
             if (ok) {
                 const int64_t idx = base + k * NC;
-                if (lambda != TC(0)) acc += lambda * ld<TC>(wJ, idx) * uc[k];
+                if (lambda != TC(0))
+                    acc += lambda * ld<TC>(wJ, (ok ? e : 0) * NP + geo_offset(col, k, NQ, W)) * uc[k];
                 acc *= oscale;
                 if (beta != TC(0)) acc += beta * static_cast<TC>(y[idx]);
                 y[idx] = static_cast<TY>(acc);

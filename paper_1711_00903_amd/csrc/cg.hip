@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "cgop.hpp"
 #include "fem.h"
 #include "fem_device.hpp"
 #include "launch.hpp"
@@ -68,12 +69,12 @@ __global__ __launch_bounds__(kRedThreads) void dot_kernel(const TA *__restrict__
 //   what == 1: pAp: alpha = rr / pAp
 //   what == 2: rr_new: beta = rr_new / rr, rr = rr_new
 enum { FIN_PLAIN = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
-__global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double *__restrict__ part, double *out,
-                                                               CgScalars *sc, int what)
+__global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double *__restrict__ part, int64_t n,
+                                                               double *out, CgScalars *sc, int what)
 {
     __shared__ double sh[kRedThreads];
     double s = 0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += part[i];
+    for (int64_t i = threadIdx.x; i < n; i += kRedThreads) s += part[i];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) {
         *out = s;
@@ -168,15 +169,20 @@ __global__ __launch_bounds__(kRedThreads) void fill_kernel(TV *__restrict__ v, i
 // ---------------------------------------------------------------------------
 // Host driver.
 // ---------------------------------------------------------------------------
+hipError_t launch_cgop_f64(const CgopArgs &, hipStream_t);
+hipError_t launch_cgop_f32g64(const CgopArgs &, hipStream_t);
+hipError_t launch_cgop_bf16g64(const CgopArgs &, hipStream_t);
+hipError_t launch_cgop_f16g64(const CgopArgs &, hipStream_t);
+
 namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
-    size_t r, tmp, xl, rl, p, Ap, part, sc, total;
+    size_t r, tmp, xl, rl, p, Ap, part, partg, sc, total;
 };
 
-Layout layout(int64_t n, size_t vbytes)
+Layout layout(int64_t n, size_t vbytes, int64_t groups)
 {
     Layout L{};
     size_t off = 0;
@@ -188,6 +194,7 @@ Layout layout(int64_t n, size_t vbytes)
     L.p = take(n * vbytes);
     L.Ap = take(n * vbytes);
     L.part = take(3 * kRedBlocks * sizeof(double));
+    L.partg = take(static_cast<size_t>(groups) * sizeof(double));
     L.sc = take(sizeof(CgScalars));
     L.total = off;
     return L;
@@ -237,13 +244,49 @@ hipError_t apply_A(const Ctx &c, int prec, const void *u, void *y)
     return launch_bp10(a, c.s);
 }
 
+// One-pass operator y = A u (optionally u <- r + beta u first), FP64 fields,
+// geometric data of precision `prec`; partials of u . y into part.
+hipError_t apply_cgop(const Ctx &c, int prec, const double *r, double *u, const double *beta, int xpay,
+                      double *y, double *part)
+{
+    const fem_cg_operator *op = c.op;
+    const bool hi = prec == FEM_F64;
+    CgopArgs a{};
+    a.N = op->N;
+    a.E = op->E;
+    a.I1d = op->I1d;
+    a.D1d = op->D1d;
+    a.G = hi ? op->G : op->G_lo;
+    a.wJ = hi ? op->wJ : op->wJ_lo;
+    const bool f16 = is_f16_prec(prec);
+    a.s_scale = f16 ? 1.0 / op->geo_scale_G : 1.0;
+    a.m_scale = f16 ? op->lambda / op->geo_scale_wJ : op->lambda;
+    a.r = r;
+    a.p = u;
+    a.beta = beta;
+    a.do_xpay = xpay;
+    a.Ap = y;
+    a.part = part;
+    switch (prec) {
+    case FEM_F64: return launch_cgop_f64(a, c.s);
+    case FEM_F32G64: return launch_cgop_f32g64(a, c.s);
+    case FEM_BF16G64: return launch_cgop_bf16g64(a, c.s);
+    case FEM_F16G64: return launch_cgop_f16g64(a, c.s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <class TV>
 int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, const double *b, double *x,
             void *ws, fem_cg_report *rep, hipStream_t s)
 {
     const int64_t np = static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
     const int64_t n = op->E * np;
-    const Layout L = layout(n, sizeof(TV));
+    const int64_t groups = cgop_groups(op->N, op->E);
+    const Layout L = layout(n, sizeof(TV), groups);
+    // the one-pass operator needs FP64 fields and a mass term
+    const bool fused = std::is_same<TV, double>::value && !opt->unfused && op->lambda != 0.0 &&
+                       cgop_supported(op->N);
     char *w = static_cast<char *>(ws);
     double *r = reinterpret_cast<double *>(w + L.r);
     double *tmp = reinterpret_cast<double *>(w + L.tmp);
@@ -254,6 +297,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     double *part = reinterpret_cast<double *>(w + L.part);
     double *part2 = part + kRedBlocks;
     double *part3 = part + 2 * kRedBlocks;
+    double *partg = reinterpret_cast<double *>(w + L.partg);
     CgScalars *sc = reinterpret_cast<CgScalars *>(w + L.sc);
     Ctx c{op, s, n, kRedBlocks};
     const dim3 G(kRedBlocks), B(kRedThreads);
@@ -263,30 +307,39 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
         if (!check(hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s))) return false;
         return check(hipStreamSynchronize(s));
     };
-    auto fin = [&](const double *pp, double *out, int what) {
-        hipLaunchKernelGGL(finalize_kernel, dim3(1), B, 0, s, pp, out, sc, what);
+    auto fin = [&](const double *pp, int64_t cnt, double *out, int what) {
+        hipLaunchKernelGGL(finalize_kernel, dim3(1), B, 0, s, pp, cnt, out, sc, what);
+    };
+    // FP64 operator applied to x into tmp
+    auto apply_hi = [&]() -> hipError_t {
+        if (fused) return apply_cgop(c, FEM_F64, nullptr, x, nullptr, 0, tmp, partg);
+        return apply_A(c, FEM_F64, x, tmp);
     };
     // true residual r = b - A x; r_lo = (TV) r.  At the start (set_p) also
     // p = r_lo and rr = r_lo.r_lo; at a reliable update the replaced r_lo.r_lo
     // goes to rr_new and its partials stay in part2, where the beta step below
     // reads them (beta = replaced rr / previous rr).
     auto true_residual = [&](bool set_p) -> hipError_t {
-        hipError_t e = apply_A(c, FEM_F64, x, tmp);
+        hipError_t e = apply_hi();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(residual_kernel<TV>, G, B, 0, s, b, tmp, r, rl, set_p ? p : nullptr, n, part,
                            part2);
-        fin(part, &sc->true_rr, FIN_PLAIN);
-        fin(part2, set_p ? &sc->rr : &sc->rr_new, FIN_PLAIN);
+        fin(part, kRedBlocks, &sc->true_rr, FIN_PLAIN);
+        fin(part2, kRedBlocks, set_p ? &sc->rr : &sc->rr_new, FIN_PLAIN);
         return hipGetLastError();
+    };
+    auto record = [&](double rel) {
+        if (opt->history && rep->history_count < opt->history_len) opt->history[rep->history_count++] = rel;
     };
 
     rep->iters = 0;
     rep->reliable_updates = 0;
     rep->hi_matvecs = 0;
+    rep->history_count = 0;
     rep->status = FEM_OK;
     if (!check(hipMemsetAsync(sc, 0, sizeof(CgScalars), s))) return FEM_ERR_HIP;
     hipLaunchKernelGGL((dot_kernel<double, double>), G, B, 0, s, b, b, n, part3);
-    fin(part3, &sc->bb, FIN_PLAIN);
+    fin(part3, kRedBlocks, &sc->bb, FIN_PLAIN);
     hipLaunchKernelGGL(fill_kernel<TV>, G, B, 0, s, xl, n);
     if (true_residual(true) != hipSuccess) return FEM_ERR_HIP;
     rep->hi_matvecs = 1;
@@ -295,17 +348,27 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     const double target = opt->rtol * bnorm;
     double rmax = std::sqrt(h.true_rr);
     double rel = bnorm > 0 ? rmax / bnorm : 0.0;
+    record(rel);
     const double delta = opt->delta > 0 ? opt->delta : 0.1;
     const int every = opt->check_every > 0 ? opt->check_every : 1;
     bool converged = rmax <= target || bnorm == 0.0;
     int it = 0;
     while (!converged && it < opt->max_iters) {
         ++it;
-        if (apply_A(c, prec_lo, p, Ap) != hipSuccess) return FEM_ERR_HIP;
-        hipLaunchKernelGGL((dot_kernel<TV, TV>), G, B, 0, s, p, Ap, n, part);
-        fin(part, &sc->pAp, FIN_ALPHA);
+        if (fused) {
+            // p <- r_lo + beta p (from the second iteration on), Ap, p . Ap
+            if (apply_cgop(c, prec_lo, reinterpret_cast<const double *>(rl), reinterpret_cast<double *>(p),
+                           &sc->beta, it > 1, reinterpret_cast<double *>(Ap), partg) != hipSuccess)
+                return FEM_ERR_HIP;
+            fin(partg, groups, &sc->pAp, FIN_ALPHA);
+        } else {
+            if (it > 1) hipLaunchKernelGGL(xpay_kernel<TV>, G, B, 0, s, p, rl, n, sc);
+            if (apply_A(c, prec_lo, p, Ap) != hipSuccess) return FEM_ERR_HIP;
+            hipLaunchKernelGGL((dot_kernel<TV, TV>), G, B, 0, s, p, Ap, n, part);
+            fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
+        }
         hipLaunchKernelGGL(update_kernel<TV>, G, B, 0, s, xl, rl, p, Ap, n, sc, part2);
-        fin(part2, &sc->rr_new, FIN_PLAIN);
+        fin(part2, kRedBlocks, &sc->rr_new, FIN_PLAIN);
         if (it % every == 0 || it == opt->max_iters) {
             if (!fetch()) return FEM_ERR_HIP;
             if (!(h.pAp > 0.0) || !std::isfinite(h.rr_new)) {
@@ -323,15 +386,16 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                 if (!fetch()) return FEM_ERR_HIP;
                 rmax = std::sqrt(h.true_rr);
                 rel = rmax / bnorm;
+                record(rel);
                 if (rmax <= target) {
                     converged = true;
                     break;
                 }
             }
         }
-        // beta = rr_new / rr; rr = rr_new; p = r_lo + beta p
-        fin(part2, &sc->rr_new, FIN_BETA);
-        hipLaunchKernelGGL(xpay_kernel<TV>, G, B, 0, s, p, rl, n, sc);
+        // beta = rr_new / rr; rr = rr_new (the direction update itself is
+        // applied at the start of the next iteration)
+        fin(part2, kRedBlocks, &sc->rr_new, FIN_BETA);
         if (hipGetLastError() != hipSuccess) return FEM_ERR_HIP;
     }
     if (!converged) {
@@ -341,6 +405,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
         rep->hi_matvecs += 1;
         if (!fetch()) return FEM_ERR_HIP;
         rel = std::sqrt(h.true_rr) / bnorm;
+        record(rel);
         converged = std::sqrt(h.true_rr) <= target;
     }
     if (!check(hipStreamSynchronize(s))) return FEM_ERR_HIP;
@@ -357,7 +422,8 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
 size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt)
 {
     const int64_t np = static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
-    return layout(op->E * np, (opt->mode == 0 || f64_fields(op->inner_prec)) ? 8 : 4).total;
+    return layout(op->E * np, (opt->mode == 0 || f64_fields(op->inner_prec)) ? 8 : 4,
+                  cgop_groups(op->N, op->E)).total;
 }
 
 int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,

@@ -151,6 +151,14 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // Bytes per value of the field vectors u and y, and of the geometric data.
 size_t field_bytes(int prec) { return f64_fields(prec) ? 8 : (prec == FEM_BF16 || prec == FEM_F16) ? 2 : 4; }
 size_t out_bytes(int prec) { return f64_fields(prec) ? 8 : 4; }
+size_t geo_bytes(int prec)
+{
+    switch (prec) {
+    case FEM_F64: return 8;
+    case FEM_F32: case FEM_F32G64: return 4;
+    default: return 2;
+    }
+}
 bool is_f16(int prec) { return is_f16_prec(prec); }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb)
@@ -245,6 +253,14 @@ int fem_geometric_factors(int N, int64_t E, int quad, const double *X, void *G, 
                                   static_cast<hipStream_t>(stream)));
 }
 
+int fem_geo_vector_width(int N, int quad, int prec)
+{
+    if (N < 1 || N > kMaxN || (quad != FEM_QUAD_GLL && quad != FEM_QUAD_GL) || prec < 0 || prec >= P_COUNT)
+        return 0;
+    const int n = quad == FEM_QUAD_GLL ? N + 1 : N + 2;
+    return geo_vec(n, static_cast<int>(geo_bytes(prec)));
+}
+
 int fem_node_coords(int N, int64_t E, int quad, const double *X, double *xyz, void *stream)
 {
     if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
@@ -318,7 +334,7 @@ static int cg_check(const fem_cg_operator *op, const fem_cg_options *opt)
     if (op->N < 1 || op->N > kMaxN || op->E < 0 || op->E > kMaxElements) return FEM_ERR_ARG;
     if (opt->mode != 0 && opt->mode != 1) return FEM_ERR_ARG;
     if (!(opt->rtol > 0.0) || opt->max_iters < 0 || opt->delta < 0.0 || opt->delta >= 1.0 ||
-        opt->check_every < 0)
+        opt->check_every < 0 || opt->history_len < 0 || (opt->history_len > 0 && !opt->history))
         return FEM_ERR_ARG;
     if (op->lambda < 0.0) return FEM_ERR_ARG;
     if (op->E == 0) return FEM_OK;

@@ -76,6 +76,48 @@ __device__ __forceinline__ TC ld_stream(const TS *__restrict__ p, int64_t idx)
 }
 
 // ---------------------------------------------------------------------------
+// Layout of geometric data (G factors and scaled Jacobians) inside one element.
+// For a tensor grid of n points per direction, node (i,j,k) -- column
+// col = i + n j -- of one factor block sits at
+//     ((k / W) n^2 + col) W + k % W,
+// i.e. the k-values of a column are interleaved in groups of W, so the thread
+// that owns the column loads W of its slabs with one vector load, and the 64
+// lanes of a wave read 64 W consecutive values.  W is the largest power of two
+// that divides n with W values in at most 16 bytes; W = 1 is the plain
+// i-fastest order.
+// ---------------------------------------------------------------------------
+constexpr int geo_vec(int n, int bytes)
+{
+    int w = 16 / bytes;
+    while (w > 1 && n % w) w >>= 1;
+    return w;
+}
+
+__host__ __device__ constexpr int64_t geo_offset(int col, int k, int n, int W)
+{
+    return (static_cast<int64_t>(k / W) * n * n + col) * W + k % W;
+}
+
+template <int BYTES> struct raw_vec;
+template <> struct raw_vec<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+template <> struct raw_vec<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct raw_vec<4> { typedef unsigned int type; };
+template <> struct raw_vec<2> { typedef unsigned short type; };
+
+// W consecutive stored values (one aligned vector), streamed non-temporally and
+// converted to the compute type.
+template <int W, class TC, class TS>
+__device__ __forceinline__ void ld_stream_vec(const TS *__restrict__ p, TC *out)
+{
+    using R = typename raw_vec<W * sizeof(TS)>::type;
+    const R v = __builtin_nontemporal_load(reinterpret_cast<const R *>(p));
+    TS tmp[W];
+    __builtin_memcpy(tmp, &v, sizeof(R));
+#pragma unroll
+    for (int r = 0; r < W; ++r) out[r] = to_compute(tmp[r], TC{});
+}
+
+// ---------------------------------------------------------------------------
 // Launch shapes.
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;

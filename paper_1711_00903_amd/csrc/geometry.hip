@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256) void geometry_kernel(int nq, int64_t E, const 
 {
     const int64_t npq = static_cast<int64_t>(nq) * nq * nq;
     const int64_t total = E * npq;
+    const int vw = geo_vec(nq, sizeof(TS));
     for (int64_t id = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; id < total;
          id += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t e = id / npq;
@@ -67,10 +68,11 @@ __global__ __launch_bounds__(256) void geometry_kernel(int nq, int64_t E, const 
         const double det = dot(ar, cr);
         if (!(det > 0.0) && bad) atomicAdd(reinterpret_cast<unsigned long long *>(bad), 1ull);
         const double w = rule.w[a] * rule.w[b] * rule.w[c];
-        if (wJ) wJ[e * npq + n] = from_double<TS>(scale * w * det);
+        const int64_t off = geo_offset(a + nq * b, c, nq, vw);
+        if (wJ) wJ[e * npq + off] = from_double<TS>(scale * w * det);
         if (G) {
             const double f = scale * w / det;
-            TS *Ge = G + e * 6 * npq + n;
+            TS *Ge = G + e * 6 * npq + off;
             Ge[0 * npq] = from_double<TS>(f * dot(cr, cr));
             Ge[1 * npq] = from_double<TS>(f * dot(cr, cs));
             Ge[2 * npq] = from_double<TS>(f * dot(cr, ct));

@@ -59,12 +59,14 @@ class CgOperator(C.Structure):
 
 class CgOptions(C.Structure):
     _fields_ = [("mode", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int),
-                ("delta", C.c_double), ("check_every", C.c_int)]
+                ("delta", C.c_double), ("check_every", C.c_int), ("unfused", C.c_int),
+                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int)]
 
 
 class CgReport(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("reliable_updates", C.c_int),
-                ("hi_matvecs", C.c_int), ("rel_res", C.c_double), ("ms", C.c_double)]
+                ("hi_matvecs", C.c_int), ("history_count", C.c_int), ("rel_res", C.c_double),
+                ("ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +81,7 @@ _SIGS = {
     "fem_geometric_factors": ([C.c_int, _i64, C.c_int, _vp, _vp, _vp, C.c_int, C.c_float, _vp, _vp],
                               C.c_int),
     "fem_node_coords": ([C.c_int, _i64, C.c_int, _vp, _vp, _vp], C.c_int),
+    "fem_geo_vector_width": ([C.c_int, C.c_int, C.c_int], C.c_int),
     "fem_mass_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_int, C.c_float, _vp],
                        C.c_int),
     "fem_stiff_collocated_apply": ([C.c_int, _i64, _vp, _vp, _vp, C.c_double, _vp, _vp, C.c_double,
@@ -182,6 +185,20 @@ def fem_supported_epb(op: int, N: int, prec: int) -> list[int]:
     if n < 0:
         raise FemError(-n, "fem_supported_epb")
     return list(buf[:n])
+
+
+def fem_geo_vector_width(N: int, quad: int, prec: int) -> int:
+    w = lib().fem_geo_vector_width(N, quad, prec)
+    if w <= 0:
+        raise FemError(FEM_ERR_ARG, "fem_geo_vector_width")
+    return w
+
+
+def geo_layout_offsets(n: int, W: int) -> np.ndarray:
+    """Stored offset of each node (natural order i + n j + n^2 k) inside one
+    factor block of the interleaved geometric-data layout of fem.h."""
+    k, col = np.divmod(np.arange(n ** 3), n * n)
+    return ((k // W) * n * n + col) * W + k % W
 
 
 # ---------------------------------------------------------------- device entry points

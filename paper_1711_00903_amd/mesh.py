@@ -6,6 +6,8 @@ tables come from ``fem_basis_tables`` (host) and the geometric factors from the
 """
 from __future__ import annotations
 
+import ctypes
+
 import numpy as np
 import torch
 
@@ -126,7 +128,8 @@ class DeviceMesh:
     # ---------------------------------------------------------------- CG
     def cg_solve(self, b, x, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
                  rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
-                 check_every: int = 1, stream=None) -> dict:
+                 check_every: int = 1, unfused: bool = False, history: int = 0,
+                 stream=None) -> dict:
         """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors."""
         G64, _ = self.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
         _, wJ64 = self.geometry(fem.FEM_QUAD_GL, fem.FEM_F64, want_G=False, kind="wJ")
@@ -140,10 +143,16 @@ class DeviceMesh:
             op.wJ_lo = wJlo.data_ptr() if lam else None
             op.geo_scale_G = self.geo_scale(inner_prec, "G")
             op.geo_scale_wJ = self.geo_scale(inner_prec, "wJ")
+        hist = (ctypes.c_double * max(1, history))()
         opt = fem.CgOptions(mode=mode, rtol=rtol, max_iters=max_iters, delta=delta,
-                            check_every=check_every)
+                            check_every=check_every, unfused=int(unfused),
+                            history=ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history else None,
+                            history_len=history)
         nbytes = fem.fem_cg_workspace_bytes(op, opt)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         rep = fem.fem_cg_solve(op, opt, b, x, ws, nbytes, stream)
         del ws
-        return rep.as_dict()
+        out = rep.as_dict()
+        if history:
+            out["history"] = list(hist[:rep.history_count])
+        return out

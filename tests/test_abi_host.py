@@ -132,9 +132,10 @@ def test_cg_struct_layout_matches_header(fem, tmp_path):
     import subprocess
     fields = {"fem_cg_operator": ("CgOperator", ["N", "E", "I1d", "D1d", "G", "wJ", "lambda", "inner_prec",
                                                  "G_lo", "wJ_lo", "geo_scale_G", "geo_scale_wJ"]),
-              "fem_cg_options": ("CgOptions", ["mode", "rtol", "max_iters", "delta", "check_every"]),
+              "fem_cg_options": ("CgOptions", ["mode", "rtol", "max_iters", "delta", "check_every",
+                                               "unfused", "history", "history_len"]),
               "fem_cg_report": ("CgReport", ["status", "iters", "reliable_updates", "hi_matvecs",
-                                             "rel_res", "ms"])}
+                                             "history_count", "rel_res", "ms"])}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "fem.h"', 'int main(void) {']
     for cs, (_, names) in fields.items():
         src.append(f'printf("%zu\\n", sizeof({cs}));')
@@ -154,3 +155,18 @@ def test_cg_struct_layout_matches_header(fem, tmp_path):
         for (pyname, _), nm in zip(S._fields_, names):
             assert getattr(S, pyname).offset == vals[k], (cs, nm)
             k += 1
+
+
+def test_geo_layout_width(fem):
+    # W: largest power of two dividing the points per direction, <= 16 bytes of values
+    assert fem.fem_geo_vector_width(7, 0, fem.FEM_F64) == 2      # 8 GLL points, FP64
+    assert fem.fem_geo_vector_width(7, 0, fem.FEM_F32) == 4
+    assert fem.fem_geo_vector_width(7, 0, fem.FEM_BF16G64) == 8
+    assert fem.fem_geo_vector_width(7, 1, fem.FEM_F64) == 1      # 9 GL points
+    assert fem.fem_geo_vector_width(5, 1, fem.FEM_F16) == 1      # 7 GL points
+    assert fem.fem_geo_vector_width(11, 0, fem.FEM_BF16) == 4    # 12 GLL points
+    for n, W in ((8, 2), (8, 8), (12, 4), (9, 1)):
+        off = fem.geo_layout_offsets(n, W)
+        assert sorted(off) == list(range(n ** 3))                # a permutation
+    off = fem.geo_layout_offsets(8, 2)
+    assert off[0] == 0 and off[64] == 1 and off[1] == 2 and off[128] == 128
