@@ -202,6 +202,33 @@ def run_cg(args) -> int:
     return 0
 
 
+def run_sweep(args) -> int:
+    """BP1.0 / BP3.5 / BP3.0 over N = 1..15 on the 64^3 mesh (E = 262144): every
+    packing timed, the fastest kept (the tune table), throughput against the
+    measured copy roofline."""
+    import torch
+
+    import workloads
+    from paper_1711_00903_amd import fem, tune
+
+    fem.lib()
+    precs = [fem.PREC_NAMES[p] for p in args.sweep_precs.split(",")]
+    Ns = [int(x) for x in args.sweep_ns.split(",")] if args.sweep_ns else list(range(1, 16))
+    X = workloads.element_vertices(args.sweep_grid)
+    copy = copy_roofline(fem, torch, 1 << 30)
+    log(f"sweep: copy roofline {copy}")
+    recs = tune.autotune(X, Ns=Ns, precs=precs, reps=args.sweep_reps, h=1.0 / args.sweep_grid, log=log)
+    for r in recs:
+        r["frac_of_copy"] = r["gbs"] / copy["best"]
+        r["frac_of_peak"] = r["gbs"] / HBM_PEAK_GBS
+    if args.tune_out:
+        with open(args.tune_out, "w") as f:
+            f.write(tune.table_text(recs))
+    print(json.dumps({"workload": f"sweep_e{X.shape[0]}", "E": X.shape[0], "copy_roofline": copy,
+                      "records": recs}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,7 +248,15 @@ def main() -> int:
     ap.add_argument("--cg-oracle", action="store_true", help="oracle re-evaluates each final residual")
     ap.add_argument("--cg-unfused", action="store_true",
                     help="separate stiffness / mass / dot / direction kernels in the CG iteration")
+    ap.add_argument("--sweep", action="store_true", help="roofline sweep over N and autotune")
+    ap.add_argument("--sweep-grid", type=int, default=64)
+    ap.add_argument("--sweep-precs", default="f64")
+    ap.add_argument("--sweep-ns", default="")
+    ap.add_argument("--sweep-reps", type=int, default=10)
+    ap.add_argument("--tune-out", default="")
     args = ap.parse_args()
+    if args.sweep:
+        return run_sweep(args)
     if args.cg:
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)

@@ -222,6 +222,42 @@ size_t fem_cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *o
 int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
                  void *workspace, size_t workspace_bytes, fem_cg_report *rep, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Ragged batches: independent applies of different meshes, degrees,
+ * operators and precisions (each descriptor is one fem_*_apply call; I1d is
+ * used by BP1.0 and BP3.0, D1d by BP3.5, Dgl by BP3.0; wJ may be NULL where the
+ * single call allows it).  All descriptors are validated before anything is
+ * enqueued.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int op;                    /* fem_op                                              */
+    int N;
+    int64_t E;
+    int prec;                  /* fem_prec                                            */
+    const double *I1d, *D1d, *Dgl;
+    const void *G, *wJ;
+    double lambda, beta;
+    float geo_scale;
+    const void *u;
+    void *y;
+} fem_apply_desc;
+
+/* DEVICE.  Enqueues the n applies on `stream` in order. */
+int fem_batch_apply(const fem_apply_desc *d, int n, void *stream);
+
+/* Captures the n applies into a HIP graph: they are spread over `lanes`
+ * (1..8) forked streams, largest first, so independent meshes may run
+ * concurrently, and joined back into `stream`.  *graph receives an opaque
+ * handle owning the graph, its executable and the forked streams.  The
+ * descriptors' buffers must stay valid until fem_batch_graph_destroy. */
+int fem_batch_graph_create(const fem_apply_desc *d, int n, int lanes, void *stream, void **graph);
+
+/* DEVICE.  One replay of the captured batch on `stream`. */
+int fem_batch_graph_launch(void *graph, void *stream);
+
+/* Releases the graph and everything it owns (synchronises its streams). */
+int fem_batch_graph_destroy(void *graph);
+
 /* Launch configuration of one (operator, degree, precision): `epb` elements per
  * workgroup (0 = library default) and `grid_cap` workgroups at most (0 = one
  * workgroup per element group, no cap).  Process-wide; affects later calls. */
@@ -232,6 +268,12 @@ int fem_tune_get(int op, int N, int prec, int *epb, int *grid_cap);
  * workgroup values of one (op, N, prec) kernel family.  `epbs` receives up to
  * `cap` values; returns their count (or a negative fem_status). */
 int fem_kernel_info(int op, int N, int prec, int epb, int *threads, int *lds_bytes);
+
+/* Loads a tune table from text: one entry per line, "op N prec epb grid_cap"
+ * (integers; '#' starts a comment).  Entries are validated like
+ * fem_tune_set; on the first bad line nothing is applied and FEM_ERR_ARG or
+ * FEM_ERR_UNSUPPORTED is returned. */
+int fem_tune_load(const char *text);
 int fem_supported_epb(int op, int N, int prec, int *epbs, int cap);
 
 #ifdef __cplusplus

@@ -4,7 +4,11 @@
 // launch-configuration table.
 #include <atomic>
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <utility>
+#include <vector>
 
 #include "fem.h"
 #include "launch.hpp"
@@ -134,6 +138,13 @@ size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt);
 int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,
              fem_cg_report *rep, hipStream_t s);
 
+int check_desc(const fem_apply_desc &d);
+int enqueue_desc(const fem_apply_desc &d, hipStream_t s);
+double desc_bytes(const fem_apply_desc &d);
+int batch_graph_create(const fem_apply_desc *d, int n, int lanes, hipStream_t s, void **graph);
+int batch_graph_launch(void *graph, hipStream_t s);
+int batch_graph_destroy(void *graph);
+
 // Process-wide launch configuration: (op, N, prec) -> (epb, grid_cap).
 static std::atomic<int> g_epb[3][kMaxN + 1][P_COUNT];
 static std::atomic<int> g_cap[3][kMaxN + 1][P_COUNT];
@@ -207,7 +218,65 @@ int run_apply(ApplyArgs &a, void *stream)
     }
 }
 
+bool dev_aligned(const void *p) { return aligned16(p); }
+
 }  // namespace
+
+namespace fem {
+
+int check_desc(const fem_apply_desc &d)
+{
+    const int st = common_checks(d.op, d.N, d.E, d.prec, d.geo_scale, d.u, d.y);
+    if (st != FEM_OK) return st;
+    if (d.op < FEM_OP_BP10 || d.op > FEM_OP_BP30) return FEM_ERR_ARG;
+    if (d.E > 0) {
+        switch (d.op) {
+        case FEM_OP_BP10:
+            if (!d.I1d || !d.wJ) return FEM_ERR_ARG;
+            if (!dev_aligned(d.wJ) || !dev_aligned(d.I1d)) return FEM_ERR_ALIGN;
+            break;
+        case FEM_OP_BP35:
+            if (!d.D1d || !d.G || (d.lambda != 0.0 && !d.wJ)) return FEM_ERR_ARG;
+            if (!dev_aligned(d.G) || !dev_aligned(d.D1d) || (d.wJ && !dev_aligned(d.wJ))) return FEM_ERR_ALIGN;
+            break;
+        default:
+            if (!d.I1d || !d.Dgl || !d.G || (d.lambda != 0.0 && !d.wJ)) return FEM_ERR_ARG;
+            if (!dev_aligned(d.G) || !dev_aligned(d.I1d) || !dev_aligned(d.Dgl) || (d.wJ && !dev_aligned(d.wJ)))
+                return FEM_ERR_ALIGN;
+        }
+    }
+    int epb, cap;
+    tune_lookup(d.op, d.N, d.prec, &epb, &cap);
+    KernelInfo ki;
+    if (!kernel_info(d.op, d.N, d.prec, epb, &ki)) return FEM_ERR_UNSUPPORTED;
+    return FEM_OK;
+}
+
+int enqueue_desc(const fem_apply_desc &d, hipStream_t s)
+{
+    ApplyArgs a{};
+    a.op = d.op; a.N = d.N; a.E = d.E; a.I1d = d.I1d; a.D1d = d.D1d; a.Dgl = d.Dgl; a.G = d.G;
+    a.wJ = d.op == FEM_OP_BP10 || d.lambda != 0.0 ? d.wJ : nullptr;
+    a.u = d.u; a.y = d.y; a.lambda = d.op == FEM_OP_BP10 ? 0.0 : d.lambda; a.beta = d.beta;
+    a.prec = d.prec; a.geo_scale = d.geo_scale;
+    return run_apply(a, s);
+}
+
+// Algorithmic HBM bytes of one descriptor (load balancing of graph lanes).
+double desc_bytes(const fem_apply_desc &d)
+{
+    const double nq = d.N + 1, ng = d.N + 2;
+    const double np = nq * nq * nq, npg = ng * ng * ng;
+    const double fb = static_cast<double>(field_bytes(d.prec)), ob = static_cast<double>(out_bytes(d.prec));
+    const double gb = static_cast<double>(geo_bytes(d.prec));
+    double geo;
+    if (d.op == FEM_OP_BP10) geo = npg * gb;
+    else if (d.op == FEM_OP_BP35) geo = (d.lambda != 0.0 ? 7.0 : 6.0) * np * gb;
+    else geo = (d.lambda != 0.0 ? 7.0 : 6.0) * npg * gb;
+    return static_cast<double>(d.E) * (np * (fb + ob + (d.beta != 0.0 ? ob : 0.0)) + geo);
+}
+
+}  // namespace fem
 
 extern "C" {
 
@@ -274,49 +343,70 @@ int fem_node_coords(int N, int64_t E, int quad, const double *X, double *xyz, vo
 int fem_mass_apply(int N, int64_t E, const double *I1d, const void *wJ, const void *u, void *y,
                    double beta, int prec, float geo_scale, void *stream)
 {
-    int st = common_checks(OP_BP10, N, E, prec, geo_scale, u, y);
-    if (st != FEM_OK) return st;
-    if (E > 0) {
-        if (!I1d || !wJ) return FEM_ERR_ARG;
-        if (!aligned16(wJ) || !aligned16(I1d)) return FEM_ERR_ALIGN;
-    }
-    ApplyArgs a{};
-    a.op = OP_BP10; a.N = N; a.E = E; a.I1d = I1d; a.wJ = wJ; a.u = u; a.y = y;
-    a.beta = beta; a.prec = prec; a.geo_scale = geo_scale;
-    return run_apply(a, stream);
+    fem_apply_desc d{};
+    d.op = FEM_OP_BP10; d.N = N; d.E = E; d.prec = prec; d.I1d = I1d; d.wJ = wJ; d.beta = beta;
+    d.geo_scale = geo_scale; d.u = u; d.y = y;
+    const int st = check_desc(d);
+    return st != FEM_OK ? st : enqueue_desc(d, static_cast<hipStream_t>(stream));
 }
 
 int fem_stiff_collocated_apply(int N, int64_t E, const double *D1d, const void *G, const void *wJ,
                                double lambda, const void *u, void *y, double beta, int prec,
                                float geo_scale, void *stream)
 {
-    int st = common_checks(OP_BP35, N, E, prec, geo_scale, u, y);
-    if (st != FEM_OK) return st;
-    if (E > 0) {
-        if (!D1d || !G || (lambda != 0.0 && !wJ)) return FEM_ERR_ARG;
-        if (!aligned16(G) || !aligned16(D1d) || (wJ && !aligned16(wJ))) return FEM_ERR_ALIGN;
-    }
-    ApplyArgs a{};
-    a.op = OP_BP35; a.N = N; a.E = E; a.D1d = D1d; a.G = G; a.wJ = wJ; a.lambda = lambda;
-    a.u = u; a.y = y; a.beta = beta; a.prec = prec; a.geo_scale = geo_scale;
-    return run_apply(a, stream);
+    fem_apply_desc d{};
+    d.op = FEM_OP_BP35; d.N = N; d.E = E; d.prec = prec; d.D1d = D1d; d.G = G; d.wJ = wJ;
+    d.lambda = lambda; d.beta = beta; d.geo_scale = geo_scale; d.u = u; d.y = y;
+    const int st = check_desc(d);
+    return st != FEM_OK ? st : enqueue_desc(d, static_cast<hipStream_t>(stream));
 }
 
 int fem_stiff_dealiased_apply(int N, int64_t E, const double *I1d, const double *Dgl, const void *G,
                               const void *wJ, double lambda, const void *u, void *y, double beta,
                               int prec, float geo_scale, void *stream)
 {
-    int st = common_checks(OP_BP30, N, E, prec, geo_scale, u, y);
-    if (st != FEM_OK) return st;
-    if (E > 0) {
-        if (!I1d || !Dgl || !G || (lambda != 0.0 && !wJ)) return FEM_ERR_ARG;
-        if (!aligned16(G) || !aligned16(I1d) || !aligned16(Dgl) || (wJ && !aligned16(wJ)))
-            return FEM_ERR_ALIGN;
+    fem_apply_desc d{};
+    d.op = FEM_OP_BP30; d.N = N; d.E = E; d.prec = prec; d.I1d = I1d; d.Dgl = Dgl; d.G = G; d.wJ = wJ;
+    d.lambda = lambda; d.beta = beta; d.geo_scale = geo_scale; d.u = u; d.y = y;
+    const int st = check_desc(d);
+    return st != FEM_OK ? st : enqueue_desc(d, static_cast<hipStream_t>(stream));
+}
+
+int fem_batch_apply(const fem_apply_desc *d, int n, void *stream)
+{
+    if (n < 0 || (n > 0 && !d)) return FEM_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        const int st = check_desc(d[i]);
+        if (st != FEM_OK) return st;
     }
-    ApplyArgs a{};
-    a.op = OP_BP30; a.N = N; a.E = E; a.I1d = I1d; a.Dgl = Dgl; a.G = G; a.wJ = wJ;
-    a.lambda = lambda; a.u = u; a.y = y; a.beta = beta; a.prec = prec; a.geo_scale = geo_scale;
-    return run_apply(a, stream);
+    for (int i = 0; i < n; ++i) {
+        const int st = enqueue_desc(d[i], static_cast<hipStream_t>(stream));
+        if (st != FEM_OK) return st;
+    }
+    return FEM_OK;
+}
+
+int fem_batch_graph_create(const fem_apply_desc *d, int n, int lanes, void *stream, void **graph)
+{
+    if (!graph || n < 0 || (n > 0 && !d) || lanes < 1 || lanes > 8 || !stream) return FEM_ERR_ARG;
+    *graph = nullptr;
+    for (int i = 0; i < n; ++i) {
+        const int st = check_desc(d[i]);
+        if (st != FEM_OK) return st;
+    }
+    return batch_graph_create(d, n, lanes, static_cast<hipStream_t>(stream), graph);
+}
+
+int fem_batch_graph_launch(void *graph, void *stream)
+{
+    if (!graph) return FEM_ERR_ARG;
+    return batch_graph_launch(graph, static_cast<hipStream_t>(stream));
+}
+
+int fem_batch_graph_destroy(void *graph)
+{
+    if (!graph) return FEM_ERR_ARG;
+    return batch_graph_destroy(graph);
 }
 
 int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
@@ -386,6 +476,41 @@ int fem_tune_set(int op, int N, int prec, int epb, int grid_cap)
     }
     g_epb[op][N][prec].store(epb, std::memory_order_relaxed);
     g_cap[op][N][prec].store(grid_cap, std::memory_order_relaxed);
+    return FEM_OK;
+}
+
+int fem_tune_load(const char *text)
+{
+    if (!text) return FEM_ERR_ARG;
+    struct Entry { int op, N, prec, epb, cap; };
+    std::vector<Entry> entries;
+    const char *line = text;
+    while (*line) {
+        const char *nl = std::strchr(line, '\n');
+        const size_t len = nl ? static_cast<size_t>(nl - line) : std::strlen(line);
+        std::string s(line, len);
+        const size_t hash = s.find('#');
+        if (hash != std::string::npos) s.resize(hash);
+        Entry e{};
+        char extra = 0;
+        const int got = std::sscanf(s.c_str(), "%d %d %d %d %d %c", &e.op, &e.N, &e.prec, &e.epb, &e.cap, &extra);
+        if (got == 5) {
+            if (e.op < 0 || e.op > 2 || e.N < 1 || e.N > kMaxN || e.prec < 0 || e.prec >= P_COUNT ||
+                e.epb < 0 || e.cap < 0)
+                return FEM_ERR_ARG;
+            KernelInfo ki;
+            if (e.epb != 0 && !kernel_info(e.op, e.N, e.prec, e.epb, &ki)) return FEM_ERR_UNSUPPORTED;
+            entries.push_back(e);
+        } else if (got > 0 || s.find_first_not_of(" \t\r") != std::string::npos) {
+            return FEM_ERR_ARG;
+        }
+        if (!nl) break;
+        line = nl + 1;
+    }
+    for (const Entry &e : entries) {
+        g_epb[e.op][e.N][e.prec].store(e.epb, std::memory_order_relaxed);
+        g_cap[e.op][e.N][e.prec].store(e.cap, std::memory_order_relaxed);
+    }
     return FEM_OK;
 }
 

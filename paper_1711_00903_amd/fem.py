@@ -72,6 +72,13 @@ class CgReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ApplyDesc(C.Structure):
+    _fields_ = [("op", C.c_int), ("N", C.c_int), ("E", C.c_int64), ("prec", C.c_int),
+                ("I1d", C.c_void_p), ("D1d", C.c_void_p), ("Dgl", C.c_void_p), ("G", C.c_void_p),
+                ("wJ", C.c_void_p), ("lam", C.c_double), ("beta", C.c_double), ("geo_scale", C.c_float),
+                ("u", C.c_void_p), ("y", C.c_void_p)]
+
+
 _SIGS = {
     "fem_status_str": ([C.c_int], C.c_char_p),
     "fem_version": ([], C.c_int),
@@ -92,6 +99,11 @@ _SIGS = {
     "fem_cg_workspace_bytes": ([C.POINTER(CgOperator), C.POINTER(CgOptions)], C.c_size_t),
     "fem_cg_solve": ([C.POINTER(CgOperator), C.POINTER(CgOptions), _vp, _vp, _vp, C.c_size_t,
                       C.POINTER(CgReport), _vp], C.c_int),
+    "fem_batch_apply": ([C.POINTER(ApplyDesc), C.c_int, _vp], C.c_int),
+    "fem_batch_graph_create": ([C.POINTER(ApplyDesc), C.c_int, C.c_int, _vp, C.POINTER(C.c_void_p)], C.c_int),
+    "fem_batch_graph_launch": ([_vp, _vp], C.c_int),
+    "fem_batch_graph_destroy": ([_vp], C.c_int),
+    "fem_tune_load": ([C.c_char_p], C.c_int),
     "fem_tune_set": ([C.c_int] * 5, C.c_int),
     "fem_tune_get": ([C.c_int, C.c_int, C.c_int, _ip, _ip], C.c_int),
     "fem_kernel_info": ([C.c_int] * 4 + [_ip, _ip], C.c_int),
@@ -251,3 +263,45 @@ def fem_cg_solve(op: CgOperator, opt: CgOptions, b, x, workspace, workspace_byte
     if raise_on_error and st not in (FEM_OK, FEM_ERR_NOT_CONVERGED, FEM_ERR_BREAKDOWN):
         raise FemError(st, "fem_cg_solve")
     return rep
+
+
+def fem_tune_load(text: str) -> None:
+    _check(lib().fem_tune_load(text.encode()), "fem_tune_load")
+
+
+def _desc_array(descs):
+    arr = (ApplyDesc * max(1, len(descs)))()
+    for i, d in enumerate(descs):
+        arr[i] = d
+    return arr
+
+
+def fem_batch_apply(descs: list, stream=None) -> None:
+    arr = _desc_array(descs)
+    _check(lib().fem_batch_apply(arr, len(descs), _stream(stream)), "fem_batch_apply")
+
+
+class BatchGraph:
+    """A captured ragged batch (fem_batch_graph_*); keeps its descriptors alive."""
+
+    def __init__(self, descs: list, lanes: int = 4, stream=None):
+        self._arr = _desc_array(descs)
+        self._descs = descs
+        h = C.c_void_p()
+        _check(lib().fem_batch_graph_create(self._arr, len(descs), lanes, _stream(stream), C.byref(h)),
+               "fem_batch_graph_create")
+        self.handle = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().fem_batch_graph_launch(self.handle, _stream(stream)), "fem_batch_graph_launch")
+
+    def destroy(self) -> None:
+        if self.handle:
+            _check(lib().fem_batch_graph_destroy(self.handle), "fem_batch_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -44,10 +44,19 @@ def default_geo_scale(h: float, kind: str) -> float:
     return float(2.0 ** round(np.log2(2.0 ** 10 / max(h, 1e-30) ** p)))
 
 
+_TUNED = [False]
+
+
 class DeviceMesh:
-    """Element vertices, 1-D tables and lazily built geometric data on one GPU."""
+    """Element vertices, 1-D tables and lazily built geometric data on one GPU.
+
+    The first instance applies the packaged MI355X tune table (if present)."""
 
     def __init__(self, N: int, X, device: str | torch.device = "cuda", h: float | None = None):
+        if not _TUNED[0]:
+            from . import tune
+            tune.load()
+            _TUNED[0] = True
         self.N = N
         self.nq, self.ng = N + 1, N + 2
         self.np, self.npg = self.nq ** 3, self.ng ** 3
@@ -156,3 +165,23 @@ class DeviceMesh:
         if history:
             out["history"] = list(hist[:rep.history_count])
         return out
+
+    # ---------------------------------------------------------------- batches
+    def desc(self, op: str, u, y, prec: int = fem.FEM_F64, lam: float = 0.0, beta: float = 0.0):
+        """Descriptor (fem_apply_desc) of one apply on this mesh, for fem_batch_*."""
+        d = fem.ApplyDesc(op=fem.OP_NAMES[op], N=self.N, E=self.E, prec=prec, lam=lam, beta=beta,
+                          u=u.data_ptr(), y=y.data_ptr())
+        if op == "BP10":
+            _, wJ = self.geometry(fem.FEM_QUAD_GL, prec, want_G=False, kind="wJ")
+            d.I1d, d.wJ, d.geo_scale = self.I1d.data_ptr(), wJ.data_ptr(), self.geo_scale(prec, "wJ")
+        else:
+            quad = fem.FEM_QUAD_GLL if op == "BP35" else fem.FEM_QUAD_GL
+            G, _ = self.geometry(quad, prec, want_wJ=False)
+            d.G, d.geo_scale = G.data_ptr(), self.geo_scale(prec)
+            if lam:
+                d.wJ = self.geometry(quad, prec, want_G=False)[1].data_ptr()
+            if op == "BP35":
+                d.D1d = self.D1d.data_ptr()
+            else:
+                d.I1d, d.Dgl = self.I1d.data_ptr(), self.Dgl.data_ptr()
+        return d

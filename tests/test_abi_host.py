@@ -170,3 +170,27 @@ def test_geo_layout_width(fem):
         assert sorted(off) == list(range(n ** 3))                # a permutation
     off = fem.geo_layout_offsets(8, 2)
     assert off[0] == 0 and off[64] == 1 and off[1] == 2 and off[128] == 128
+
+
+def test_tune_load(fem):
+    before = fem.fem_tune_get(fem.FEM_OP_BP10, 7, fem.FEM_F64)
+    fem.fem_tune_load("# op N prec epb cap\n0 7 0 3 0\n1 7 0 1 512  # comment\n\n")
+    assert fem.fem_tune_get(fem.FEM_OP_BP10, 7, fem.FEM_F64) == (3, 0)
+    assert fem.fem_tune_get(fem.FEM_OP_BP35, 7, fem.FEM_F64) == (1, 512)
+    for bad, st in (("0 7 0 3\n", fem.FEM_ERR_ARG), ("0 7 0 999 0\n", fem.FEM_ERR_UNSUPPORTED),
+                    ("0 16 0 1 0\n", fem.FEM_ERR_ARG), ("garbage\n", fem.FEM_ERR_ARG)):
+        with pytest.raises(fem.FemError) as ei:
+            fem.fem_tune_load("0 7 0 1 0\n" + bad)      # nothing applied on error
+        assert ei.value.status == st
+        assert fem.fem_tune_get(fem.FEM_OP_BP10, 7, fem.FEM_F64) == (3, 0)
+    fem.fem_tune_load("0 7 0 0 0\n1 7 0 0 0\n")
+    assert fem.fem_tune_get(fem.FEM_OP_BP10, 7, fem.FEM_F64)[0] == before[0]
+
+
+def test_batch_validation_on_host(fem):
+    d = fem.ApplyDesc(op=1, N=7, E=4, prec=0, D1d=0x1000, G=0x2000, u=0x3000, y=1 << 40)
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_batch_apply([d, fem.ApplyDesc(op=5, N=7, E=4)], stream=0)
+    assert ei.value.status == fem.FEM_ERR_ARG
+    with pytest.raises(fem.FemError):
+        fem.BatchGraph([d], lanes=9, stream=0)
