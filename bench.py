@@ -155,14 +155,14 @@ def run_cg(args) -> int:
             dev.geometry(fem.FEM_QUAD_GL, prec, want_G=False, kind="wJ")
     torch.cuda.synchronize()
     out = {"workload": f"cg_n7_e{E}", "E": E, "N": Ncg, "dofs": E * (Ncg + 1) ** 3, "lambda": 1.0,
-           "fused": not args.cg_unfused, "arms": {}}
+           "fusion": args.cg_fusion, "arms": {}}
     tau = args.cg_rtol
     if args.cg_floor_iters > 0:
         # attainable FP64 accuracy: run FP64 CG far past convergence and take the
         # median true residual over the second half of its reliable updates
         x = torch.zeros_like(b)
         rep = dev.cg_solve(b, x, lam=1.0, mode=0, rtol=1e-16, max_iters=args.cg_floor_iters,
-                           unfused=args.cg_unfused, history=4096)
+                           fusion=fem.FUSION_NAMES[args.cg_fusion], history=4096)
         hist = rep.pop("history")
         tail = sorted(hist[len(hist) // 2:])
         floor = tail[len(tail) // 2]
@@ -176,7 +176,7 @@ def run_cg(args) -> int:
         x = torch.zeros_like(b)
         maxit = args.cg_max_iters if name != "f32" else min(args.cg_max_iters, 4000)
         rep = dev.cg_solve(b, x, lam=1.0, mode=mode, inner_prec=prec, rtol=tau, max_iters=maxit,
-                           unfused=args.cg_unfused)
+                           fusion=fem.FUSION_NAMES[args.cg_fusion])
         log(f"cg: {name}: {rep}")
         rec = dict(rep)
         if args.cg_oracle:
@@ -217,7 +217,8 @@ def run_sweep(args) -> int:
     X = workloads.element_vertices(args.sweep_grid)
     copy = copy_roofline(fem, torch, 1 << 30)
     log(f"sweep: copy roofline {copy}")
-    recs = tune.autotune(X, Ns=Ns, precs=precs, reps=args.sweep_reps, h=1.0 / args.sweep_grid, log=log)
+    recs = tune.autotune(X, ops=tuple(args.sweep_ops.split(",")), Ns=Ns, precs=precs,
+                         reps=args.sweep_reps, h=1.0 / args.sweep_grid, log=log)
     for r in recs:
         r["frac_of_copy"] = r["gbs"] / copy["best"]
         r["frac_of_peak"] = r["gbs"] / HBM_PEAK_GBS
@@ -246,12 +247,13 @@ def main() -> int:
     ap.add_argument("--cg-max-iters", type=int, default=20000)
     ap.add_argument("--cg-arms", default="fp64,f32g64,bf16g64,f16g64,f32")
     ap.add_argument("--cg-oracle", action="store_true", help="oracle re-evaluates each final residual")
-    ap.add_argument("--cg-unfused", action="store_true",
-                    help="separate stiffness / mass / dot / direction kernels in the CG iteration")
+    ap.add_argument("--cg-fusion", default="auto", choices=["auto", "none", "onepass"],
+                    help="kernel split of the CG iteration (fem_cg_fusion)")
     ap.add_argument("--sweep", action="store_true", help="roofline sweep over N and autotune")
     ap.add_argument("--sweep-grid", type=int, default=64)
     ap.add_argument("--sweep-precs", default="f64")
     ap.add_argument("--sweep-ns", default="")
+    ap.add_argument("--sweep-ops", default="BP10,BP35,BP30")
     ap.add_argument("--sweep-reps", type=int, default=10)
     ap.add_argument("--tune-out", default="")
     args = ap.parse_args()

@@ -186,15 +186,23 @@ typedef struct {
     float geo_scale_wJ;        /* FP16 inner mode: storage scale of wJ_lo             */
 } fem_cg_operator;
 
+/* How one Krylov iteration's p <- r + beta p, Ap = (S + lambda M) p and p . Ap
+ * are split into kernels.  AUTO: two kernels where available (FP64 vectors,
+ * N <= 7, lambda != 0) -- the stiffness kernel forms p as it loads it and
+ * writes it back, the mass kernel adds lambda M p and emits per-element
+ * partials of p . Ap -- else as NONE.  NONE: one kernel per step.  ONEPASS: a
+ * single kernel for the three steps (FP64 vectors, lambda != 0, N <= 14),
+ * else as NONE.  All three give the same iterates up to rounding. */
+typedef enum { FEM_CG_FUSE_AUTO = 0, FEM_CG_FUSE_NONE = 1, FEM_CG_FUSE_ONEPASS = 2 } fem_cg_fusion;
+
 typedef struct {
     int mode;                  /* 0 = FP64 CG, 1 = mixed precision                    */
     double rtol;               /* relative FP64 true-residual target                  */
     int max_iters;             /* iterations of the Krylov loop                       */
     double delta;              /* reliable-update threshold, (0, 1); 0 = 0.1          */
     int check_every;           /* host residual check period; 0 = 1                   */
-    int unfused;               /* 1: separate stiffness, mass, dot and direction      */
-                               /* kernels; 0: the one-pass operator kernel (FP64      */
-                               /* vectors) that also updates p and forms p . Ap       */
+    int fusion;                /* fem_cg_fusion: how the Krylov step is split into    */
+                               /* kernels                                             */
     double *history;           /* HOST array or NULL: the true relative residual at   */
                                /* the start and after each reliable update           */
     int history_len;           /* capacity of history                                 */

@@ -14,6 +14,7 @@
 #pragma once
 
 #include "bp35.hpp"
+#include "bp10w.hpp"
 
 namespace fem {
 
@@ -177,6 +178,7 @@ hipError_t bp10_launch_t(const ApplyArgs &a, hipStream_t s)
 {
     using TC = typename compute_pair<TG, TV>::type;
     using TY = typename output_of<TV>::type;
+    if (a.part) return hipErrorInvalidValue;   // element partials: one-wave kernel only
     const int64_t ngroups = (a.E + EPB - 1) / EPB;
     int64_t grid = ngroups;
     if (a.grid_cap > 0 && grid > a.grid_cap) grid = a.grid_cap;
@@ -195,7 +197,10 @@ hipError_t bp10_launch_nq(const ApplyArgs &a, hipStream_t s)
 {
     constexpr auto ch = epb_choices(0, NQ);
     const int epb = a.epb > 0 ? a.epb : epb_default(0, NQ);
-    if (epb == ch[0]) return bp10_launch_t<NQ, ch[0], TG, TV>(a, s);
+    if (epb == ch[0]) {
+        if constexpr (bp10_wave(NQ, ch[0])) return bp10w_launch_t<NQ, TG, TV>(a, s);
+        else return bp10_launch_t<NQ, ch[0], TG, TV>(a, s);
+    }
     if constexpr (ch[1] > 0) if (epb == ch[1]) return bp10_launch_t<NQ, ch[1], TG, TV>(a, s);
     if constexpr (ch[2] > 0) if (epb == ch[2]) return bp10_launch_t<NQ, ch[2], TG, TV>(a, s);
     if constexpr (ch[3] > 0) if (epb == ch[3]) return bp10_launch_t<NQ, ch[3], TG, TV>(a, s);

@@ -36,14 +36,20 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
     constexpr int R1 = R1a > R1b ? (R1a > R1c ? R1a : R1c) : (R1b > R1c ? R1b : R1c);
     constexpr int R2a = NQ * NQ * PG, R2b = NG * NG * PG;
     constexpr int R2 = R2a > R2b ? R2a : R2b;
-    constexpr int R3 = NG * NG * PG;
-    constexpr int SLOT = R1 + R2 + R3;
+    constexpr int SLOT = bp30_slot_values(NQ, sizeof(TC));
+    static_assert(SLOT == R1 + R2 + NG * NG * PG, "LDS slot layout");
+    // the element's 6 Ng^3 geometric factors go to LDS by direct loads at the
+    // start of each element (when they fit): all of its G traffic is in flight
+    // from the first instruction on, without holding registers
+    constexpr bool GLDS = bp30_glds(NQ, EPB, sizeof(TC), sizeof(TG));
+    constexpr int NT = threads_for(2, NQ, EPB);
     constexpr bool TREG = NQ <= 6;
     constexpr int W = geo_vec(NG, sizeof(TG));   // Gauss slabs per vector load of G / wJ
 
     __shared__ TC s_I[NG * NQ];
     __shared__ TC s_D[NG * NG];
     __shared__ TC s_w[EPB * SLOT];
+    __shared__ __align__(16) TG s_g[GLDS ? 6 * NPG : 1];
 
     const int t = threadIdx.x;
     const int slot = t / NCG;
@@ -78,6 +84,8 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
 
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t e0 = g * EPB;
+        // (with GLDS, EPB == 1 and e0 < E: the group's one element is valid)
+        if constexpr (GLDS) lds_dma<6 * NPG * sizeof(TG), NT>(s_g, G + e0 * (6 * NPG));
         {
             const int nvalid = static_cast<int>((E - e0) < EPB ? (E - e0) : EPB);
             stage_fields<NQ, EPB, threads_for(2, NQ, EPB), SLOT, PQ>(s_w, u + e0 * NP, nvalid);
@@ -141,7 +149,15 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
                 qt += uniform_entry(Dgl, s_D, c * NG + m) * qg[m];
             }
             TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
-            if (ok) {
+            if constexpr (GLDS) {
+                const int64_t o = geo_offset(col, c, NG, W);
+                grr = to_compute(s_g[0 * NPG + o], TC{});
+                grs = to_compute(s_g[1 * NPG + o], TC{});
+                grt = to_compute(s_g[2 * NPG + o], TC{});
+                gss = to_compute(s_g[3 * NPG + o], TC{});
+                gst = to_compute(s_g[4 * NPG + o], TC{});
+                gtt = to_compute(s_g[5 * NPG + o], TC{});
+            } else if (ok) {
                 if (c % W == 0) {
 #pragma unroll
                     for (int f = 0; f < 6; ++f) ld_stream_vec<W>(Ge + f * NPG + (c / W) * NCG * W, gw + f * W);

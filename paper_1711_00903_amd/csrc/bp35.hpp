@@ -76,12 +76,16 @@ __device__ __forceinline__ void stage_fields(TC *__restrict__ s_w, const TV *__r
     }
 }
 
-template <int NQ, int EPB, class TG, class TV>
+// XP: the conjugate-gradient direction update p <- r + beta_p p is applied to
+// u in place as it is loaded (u is then read and written through `pw`, r is
+// `xr`, beta_p is *xbeta), so the operator acts on the updated p.
+template <int NQ, int EPB, class TG, class TV, bool XP = false>
 __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     int64_t E, int64_t ngroups, const double *__restrict__ D1d, const TG *__restrict__ G,
     const TG *__restrict__ wJ, typename compute_pair<TG, TV>::type lambda, const TV *__restrict__ u,
     typename output_of<TV>::type *__restrict__ y, typename compute_pair<TG, TV>::type beta,
-    typename compute_pair<TG, TV>::type oscale)
+    typename compute_pair<TG, TV>::type oscale, TV *pw = nullptr, const TV *__restrict__ xr = nullptr,
+    const double *__restrict__ xbeta = nullptr)
 {
     using TC = typename compute_pair<TG, TV>::type;
     using TY = typename output_of<TV>::type;
@@ -132,8 +136,24 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         const int64_t base = (ok ? e : 0) * NP + col;
 
         TC uc[NQ];
+        if constexpr (XP) {
+            static_assert(std::is_same<TV, double>::value, "direction update on FP64 fields");
+            const double bp = *xbeta;
+            double rv[NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
+            for (int k = 0; k < NQ; ++k) {
+                uc[k] = ok ? pw[base + k * NC] : 0.0;
+                rv[k] = ok ? xr[base + k * NC] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                uc[k] = rv[k] + bp * uc[k];
+                if (ok) pw[base + k * NC] = uc[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
+        }
         const TG *Ge = G + (ok ? e : 0) * (6 * NP) + col * W;
         TC gp[PREF ? 6 * NQ : 1];   // gp[f * NQ + k]: factor f at slab k
         if constexpr (PREF) {
@@ -235,6 +255,18 @@ hipError_t bp35_launch_t(const ApplyArgs &a, hipStream_t s)
     if (grid < 1) return hipSuccess;
     const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
                                                                          : a.out_scale);
+    if constexpr (std::is_same<TV, double>::value) {
+        if (a.xr) {
+            hipLaunchKernelGGL((bp35_kernel<NQ, EPB, TG, TV, true>), dim3(static_cast<unsigned>(grid)),
+                               dim3(threads_for(1, NQ, EPB)), 0, s, a.E, ngroups, a.D1d,
+                               static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
+                               static_cast<TC>(a.lambda), static_cast<const TV *>(a.u),
+                               static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale,
+                               static_cast<TV *>(const_cast<void *>(a.u)), a.xr, a.xbeta);
+            return hipGetLastError();
+        }
+    }
+    if (a.xr) return hipErrorInvalidValue;
     hipLaunchKernelGGL((bp35_kernel<NQ, EPB, TG, TV>), dim3(static_cast<unsigned>(grid)),
                        dim3(threads_for(1, NQ, EPB)), 0, s, a.E, ngroups, a.D1d,
                        static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),

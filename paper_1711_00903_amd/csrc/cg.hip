@@ -64,6 +64,19 @@ __global__ __launch_bounds__(kRedThreads) void dot_kernel(const TA *__restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Partial sums of v[0..n) per block, in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void sum_kernel(const double *__restrict__ v, int64_t n,
+                                                          double *__restrict__ part)
+{
+    __shared__ double sh[kRedThreads];
+    double s = 0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads)
+        s += v[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // Final reduction of kRedBlocks partials into *out, then a scalar step:
 //   what == 0: out = rr (nothing else)
 //   what == 1: pAp: alpha = rr / pAp
@@ -178,6 +191,14 @@ namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
+// Entries of the per-group partial-sum buffer: one per workgroup of the
+// one-pass operator, one per element of the two-kernel form.
+int64_t cg_groups(int N, int64_t E)
+{
+    const int64_t g = cgop_groups(N, E);
+    return g > E ? g : E;
+}
+
 struct Layout {
     size_t r, tmp, xl, rl, p, Ap, part, partg, sc, total;
 };
@@ -244,6 +265,47 @@ hipError_t apply_A(const Ctx &c, int prec, const void *u, void *y)
     return launch_bp10(a, c.s);
 }
 
+// Two-kernel Krylov operator on FP64 vectors: the stiffness kernel applies the
+// direction update u <- r + (*beta) u as it loads u (when r is set), the mass
+// kernel (one-wave BP1.0) adds lambda M u and writes per-element partials of
+// u . y into epart.  Requires N <= 7 and lambda != 0.
+hipError_t apply_A_split(const Ctx &c, int prec, const double *r, const double *beta, double *u, double *y,
+                         double *epart)
+{
+    const fem_cg_operator *op = c.op;
+    const bool hi = prec == FEM_F64;
+    ApplyArgs a{};
+    a.N = op->N;
+    a.E = op->E;
+    a.I1d = op->I1d;
+    a.D1d = op->D1d;
+    a.u = u;
+    a.y = y;
+    a.prec = prec;
+    a.op = OP_BP35;
+    a.G = hi ? op->G : op->G_lo;
+    a.geo_scale = op->geo_scale_G;
+    a.xr = r;
+    a.xbeta = beta;
+    fem_tune_get(OP_BP35, a.N, prec, &a.epb, &a.grid_cap);
+    hipError_t e = launch_bp35(a, c.s);
+    if (e != hipSuccess) return e;
+    a.op = OP_BP10;
+    a.G = nullptr;
+    a.wJ = hi ? op->wJ : op->wJ_lo;
+    a.beta = 1.0;
+    a.out_scale = op->lambda;
+    a.geo_scale = op->geo_scale_wJ;
+    a.xr = nullptr;
+    a.xbeta = nullptr;
+    a.part = epart;
+    a.epb = 1;          // the one-wave kernel
+    a.grid_cap = 0;
+    return launch_bp10(a, c.s);
+}
+
+inline bool split_supported(int N) { return N + 1 <= 8; }
+
 // One-pass operator y = A u (optionally u <- r + beta u first), FP64 fields,
 // geometric data of precision `prec`; partials of u . y into part.
 hipError_t apply_cgop(const Ctx &c, int prec, const double *r, double *u, const double *beta, int xpay,
@@ -282,11 +344,12 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
 {
     const int64_t np = static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
     const int64_t n = op->E * np;
-    const int64_t groups = cgop_groups(op->N, op->E);
+    const int64_t groups = cg_groups(op->N, op->E);
     const Layout L = layout(n, sizeof(TV), groups);
-    // the one-pass operator needs FP64 fields and a mass term
-    const bool fused = std::is_same<TV, double>::value && !opt->unfused && op->lambda != 0.0 &&
-                       cgop_supported(op->N);
+    // the fused forms need FP64 vectors and a mass term
+    const bool f64v = std::is_same<TV, double>::value && op->lambda != 0.0;
+    const bool fused = f64v && opt->fusion == FEM_CG_FUSE_ONEPASS && cgop_supported(op->N);
+    const bool split = f64v && opt->fusion == FEM_CG_FUSE_AUTO && split_supported(op->N);
     char *w = static_cast<char *>(ws);
     double *r = reinterpret_cast<double *>(w + L.r);
     double *tmp = reinterpret_cast<double *>(w + L.tmp);
@@ -361,6 +424,12 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                            &sc->beta, it > 1, reinterpret_cast<double *>(Ap), partg) != hipSuccess)
                 return FEM_ERR_HIP;
             fin(partg, groups, &sc->pAp, FIN_ALPHA);
+        } else if (split) {
+            if (apply_A_split(c, prec_lo, it > 1 ? reinterpret_cast<const double *>(rl) : nullptr, &sc->beta,
+                              reinterpret_cast<double *>(p), reinterpret_cast<double *>(Ap), partg) != hipSuccess)
+                return FEM_ERR_HIP;
+            hipLaunchKernelGGL(sum_kernel, G, B, 0, s, partg, op->E, part);
+            fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
         } else {
             if (it > 1) hipLaunchKernelGGL(xpay_kernel<TV>, G, B, 0, s, p, rl, n, sc);
             if (apply_A(c, prec_lo, p, Ap) != hipSuccess) return FEM_ERR_HIP;
@@ -423,7 +492,7 @@ size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt)
 {
     const int64_t np = static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
     return layout(op->E * np, (opt->mode == 0 || f64_fields(op->inner_prec)) ? 8 : 4,
-                  cgop_groups(op->N, op->E)).total;
+                  cg_groups(op->N, op->E)).total;
 }
 
 int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,

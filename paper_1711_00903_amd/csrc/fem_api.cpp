@@ -120,6 +120,15 @@ int default_epb(int op, int N, int prec)
     return epb_default(op, N + 1);
 }
 
+static int geo_value_bytes(int prec)
+{
+    switch (prec) {
+    case P_F64: return 8;
+    case P_F32: case P_F32G64: return 4;
+    default: return 2;
+    }
+}
+
 bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
 {
     int ch[kMaxEpbChoices];
@@ -130,7 +139,7 @@ bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
     if (!found) return false;
     const int bytes = f64_fields(prec) ? 8 : 4;   // compute type held in LDS
     info->threads = threads_for(op, N + 1, epb);
-    info->lds_bytes = lds_bytes(op, N + 1, epb, bytes);
+    info->lds_bytes = lds_bytes(op, N + 1, epb, bytes, geo_value_bytes(prec));
     return true;
 }
 
@@ -423,6 +432,7 @@ static int cg_check(const fem_cg_operator *op, const fem_cg_options *opt)
     if (!op || !opt) return FEM_ERR_ARG;
     if (op->N < 1 || op->N > kMaxN || op->E < 0 || op->E > kMaxElements) return FEM_ERR_ARG;
     if (opt->mode != 0 && opt->mode != 1) return FEM_ERR_ARG;
+    if (opt->fusion < FEM_CG_FUSE_AUTO || opt->fusion > FEM_CG_FUSE_ONEPASS) return FEM_ERR_ARG;
     if (!(opt->rtol > 0.0) || opt->max_iters < 0 || opt->delta < 0.0 || opt->delta >= 1.0 ||
         opt->check_every < 0 || opt->history_len < 0 || (opt->history_len > 0 && !opt->history))
         return FEM_ERR_ARG;

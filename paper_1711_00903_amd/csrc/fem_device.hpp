@@ -9,6 +9,9 @@
 
 namespace fem {
 
+constexpr int kWave = 64;
+constexpr int kWaveDma = kWave;
+
 // ---------------------------------------------------------------------------
 // Storage types.  u, G and wJ are stored in one of four precisions; FP64
 // storage computes in FP64, the others in FP32.
@@ -118,9 +121,39 @@ __device__ __forceinline__ void ld_stream_vec(const TS *__restrict__ p, TC *out)
 }
 
 // ---------------------------------------------------------------------------
+// Direct global -> LDS copy (gfx950 LDS DMA): `bytes` contiguous bytes from
+// `src` to `dst`, issued by all `nt` threads of the workgroup in 16-byte (or,
+// when the block or its alignment does not allow it, 4-byte) pieces.  The data
+// never passes through registers; it is complete after the next workgroup
+// barrier (the compiler waits for the outstanding loads before the barrier).
+// The LDS address of each instruction is wave-uniform: lane l of the wave
+// writes piece (wave base + l).
+// ---------------------------------------------------------------------------
+template <int BYTES, int NT>
+__device__ __forceinline__ void lds_dma(void *dst, const void *src)
+{
+    constexpr int CH = (BYTES % 16 == 0) ? 16 : 4;
+    static_assert(BYTES % 4 == 0, "LDS DMA moves whole dwords");
+    constexpr int NCH = BYTES / CH;
+    const int lane = threadIdx.x & (kWaveDma - 1);
+    const int wave0 = threadIdx.x - lane;
+#pragma unroll
+    for (int s = 0; s < (NCH + NT - 1) / NT; ++s) {
+        const int x = static_cast<int>(threadIdx.x) + s * NT;
+        if (x < NCH) {
+            auto *d = reinterpret_cast<__attribute__((address_space(3))) char *>(
+                reinterpret_cast<uintptr_t>(dst) + static_cast<uintptr_t>(wave0 + s * NT) * CH);
+            const char *g = static_cast<const char *>(src) + static_cast<int64_t>(x) * CH;
+            auto *l = reinterpret_cast<__attribute__((address_space(3))) void *>(d);
+            if constexpr (CH == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+            else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launch shapes.
 // ---------------------------------------------------------------------------
-constexpr int kWave = 64;
 constexpr int round_up_wave(int n) { return (n + kWave - 1) / kWave * kWave; }
 
 // Row length (in values) of an LDS slab whose rows hold `n` values of `bytes`

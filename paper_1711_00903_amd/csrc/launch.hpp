@@ -37,6 +37,14 @@ struct ApplyArgs {
     int prec;
     int epb;             // elements per workgroup, 0 = default
     int grid_cap;        // max workgroups, 0 = uncapped
+    // Conjugate-gradient extensions (FP64 fields only).  BP3.5 with xr set
+    // first replaces u in place by xr + (*xbeta) u (the direction update) and
+    // applies the operator to the result.  BP1.0 (one-wave kernel) with part
+    // set writes part[e] = sum over element e's nodes of u * y, y the final
+    // output.
+    const double *xr = nullptr;
+    const double *xbeta = nullptr;
+    double *part = nullptr;
 };
 
 struct KernelInfo {

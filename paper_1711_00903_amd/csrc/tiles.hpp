@@ -3,7 +3,9 @@
 // Every kernel maps one thread to one (i,j) column of an element (a vertical
 // line of nodes along t) and packs `epb` elements into one workgroup.  BP3.5
 // works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
-// (the GLL phases use a subset of those threads).
+// (the GLL phases use a subset of those threads).  One exception: BP1.0 with
+// one element per workgroup and Nq <= 8 runs one wave per element with the
+// even-odd contractions of bp10w.hpp.
 #pragma once
 
 #include <array>
@@ -17,25 +19,60 @@ constexpr int kMaxLds = 160 * 1024;   // gfx950 LDS per workgroup
 
 constexpr int columns(int op, int nq) { return op == 1 ? nq * nq : (nq + 1) * (nq + 1); }
 
-// LDS bytes of one workgroup for values of `bytes` bytes (tables included).
-constexpr int lds_bytes(int op, int nq, int epb, int bytes)
+// BP3.0 stages each element's geometric factors (6 Ng^3 values of `gbytes`
+// bytes) in LDS by direct global -> LDS loads when one element per workgroup
+// fits in 96 KiB with them (two workgroups per CU).
+constexpr int bp30_slot_values(int nq, int bytes)
 {
     const int ng = nq + 1;
     const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
+    const int r1a = nq * nq * pq, r1b = ng * ng * pg, r1c = nq * ng * pg;
+    const int r1 = r1a > r1b ? (r1a > r1c ? r1a : r1c) : (r1b > r1c ? r1b : r1c);
+    const int r2a = nq * nq * pg, r2b = ng * ng * pg;
+    const int r2 = r2a > r2b ? r2a : r2b;
+    return r1 + r2 + ng * ng * pg;
+}
+
+constexpr bool bp30_glds(int nq, int epb, int cbytes, int gbytes)
+{
+    const int ng = nq + 1;
+    const int gb = 6 * ng * ng * ng * gbytes;
+    return epb == 1 && gb % 4 == 0 && bp30_slot_values(nq, cbytes) * cbytes + gb <= 96 * 1024;
+}
+
+// BP1.0 with one element per workgroup and Nq <= 8 runs the one-wave
+// even-odd kernel (bp10w.hpp).
+constexpr bool bp10_wave(int nq, int epb) { return epb == 1 && nq <= 8; }
+
+constexpr int bp10w_lds_bytes(int nq, int bytes)
+{
+    const int ng = nq + 1, hg = (ng + 1) / 2, hq = (nq + 1) / 2;
+    const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
+    const int su = nq * nq * pq, sb = nq * ng * pg;
+    const int full = bytes == 8 ? 1 : ng * nq;   // FP64 reads the full table from global memory
+    return (4 * hg * hq + full + (su > sb ? su : sb) + nq * nq * pg) * bytes;
+}
+
+// LDS bytes of one workgroup for values of `bytes` bytes (tables included);
+// gbytes: stored size of a geometric value (BP3.0 LDS staging).
+constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
+{
+    const int ng = nq + 1;
+    const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
+    if (op == 0 && bp10_wave(nq, epb)) return bp10w_lds_bytes(nq, bytes);
     if (op == 1) return (nq * nq + 3 * epb * nq * nq * pq) * bytes;
     if (op == 0) {
         const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
         return (ng * nq + epb * slot) * bytes;
     }
-    const int r1a = nq * nq * pq, r1b = ng * ng * pg, r1c = nq * ng * pg;
-    const int r1 = r1a > r1b ? (r1a > r1c ? r1a : r1c) : (r1b > r1c ? r1b : r1c);
-    const int r2a = nq * nq * pg, r2b = ng * ng * pg;
-    const int r2 = r2a > r2b ? r2a : r2b;
-    const int r3 = ng * ng * pg;
-    return (ng * nq + ng * ng + epb * (r1 + r2 + r3)) * bytes;
+    const int gstage = bp30_glds(nq, epb, bytes, gbytes) ? 6 * ng * ng * ng * gbytes : 0;
+    return (ng * nq + ng * ng + epb * bp30_slot_values(nq, bytes)) * bytes + gstage;
 }
 
-constexpr int threads_for(int op, int nq, int epb) { return round_up_wave(columns(op, nq) * epb); }
+constexpr int threads_for(int op, int nq, int epb)
+{
+    return op == 0 && bp10_wave(nq, epb) ? kWave : round_up_wave(columns(op, nq) * epb);
+}
 
 // Up to four supported elements-per-workgroup values: 1, then those that fill
 // at least 80% of the lanes of the workgroup's waves within the thread and

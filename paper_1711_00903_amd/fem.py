@@ -32,6 +32,8 @@ FEM_F64, FEM_F32, FEM_BF16, FEM_F16, FEM_BF16G, FEM_F16G = 0, 1, 2, 3, 4, 5
 FEM_F32G64, FEM_BF16G64, FEM_F16G64 = 6, 7, 8
 FEM_OP_BP10, FEM_OP_BP35, FEM_OP_BP30 = 0, 1, 2
 FEM_QUAD_GLL, FEM_QUAD_GL = 0, 1
+FEM_CG_FUSE_AUTO, FEM_CG_FUSE_NONE, FEM_CG_FUSE_ONEPASS = 0, 1, 2
+FUSION_NAMES = {"auto": FEM_CG_FUSE_AUTO, "none": FEM_CG_FUSE_NONE, "onepass": FEM_CG_FUSE_ONEPASS}
 
 PREC_NAMES = {"f64": FEM_F64, "f32": FEM_F32, "bf16": FEM_BF16, "f16": FEM_F16,
               "bf16g": FEM_BF16G, "f16g": FEM_F16G, "f32g64": FEM_F32G64,
@@ -59,7 +61,7 @@ class CgOperator(C.Structure):
 
 class CgOptions(C.Structure):
     _fields_ = [("mode", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int),
-                ("delta", C.c_double), ("check_every", C.c_int), ("unfused", C.c_int),
+                ("delta", C.c_double), ("check_every", C.c_int), ("fusion", C.c_int),
                 ("history", C.POINTER(C.c_double)), ("history_len", C.c_int)]
 
 

@@ -137,7 +137,7 @@ class DeviceMesh:
     # ---------------------------------------------------------------- CG
     def cg_solve(self, b, x, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
                  rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
-                 check_every: int = 1, unfused: bool = False, history: int = 0,
+                 check_every: int = 1, fusion: int = fem.FEM_CG_FUSE_AUTO, history: int = 0,
                  stream=None) -> dict:
         """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors."""
         G64, _ = self.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
@@ -154,7 +154,7 @@ class DeviceMesh:
             op.geo_scale_wJ = self.geo_scale(inner_prec, "wJ")
         hist = (ctypes.c_double * max(1, history))()
         opt = fem.CgOptions(mode=mode, rtol=rtol, max_iters=max_iters, delta=delta,
-                            check_every=check_every, unfused=int(unfused),
+                            check_every=check_every, fusion=int(fusion),
                             history=ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history else None,
                             history_len=history)
         nbytes = fem.fem_cg_workspace_bytes(op, opt)

@@ -73,6 +73,10 @@ def test_tune_table(fem):
                 th, lds = fem.fem_kernel_info(op, N, fem.FEM_F64, c)
                 assert th % 64 == 0 and 64 <= th <= 512
                 assert 0 < lds <= 160 * 1024
+    # BP1.0 with one element per workgroup runs one wave per element up to N = 7
+    for N in range(1, 16):
+        th, _ = fem.fem_kernel_info(fem.FEM_OP_BP10, N, fem.FEM_F64, 1)
+        assert (th == 64) == (N <= 7), (N, th)
     fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 2, 1024)
     assert fem.fem_tune_get(fem.FEM_OP_BP35, 7, fem.FEM_F64) == (2, 1024)
     fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 0, 0)
@@ -133,7 +137,7 @@ def test_cg_struct_layout_matches_header(fem, tmp_path):
     fields = {"fem_cg_operator": ("CgOperator", ["N", "E", "I1d", "D1d", "G", "wJ", "lambda", "inner_prec",
                                                  "G_lo", "wJ_lo", "geo_scale_G", "geo_scale_wJ"]),
               "fem_cg_options": ("CgOptions", ["mode", "rtol", "max_iters", "delta", "check_every",
-                                               "unfused", "history", "history_len"]),
+                                               "fusion", "history", "history_len"]),
               "fem_cg_report": ("CgReport", ["status", "iters", "reliable_updates", "hi_matvecs",
                                              "history_count", "rel_res", "ms"])}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "fem.h"', 'int main(void) {']

@@ -58,12 +58,15 @@ def test_rhs_agrees(setup):
     np.testing.assert_allclose(bt.cpu().numpy(), bo, rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("unfused", [False, True])
+FUSIONS = [0, 1, 2]   # auto (two kernels), none, one-pass
+
+
+@pytest.mark.parametrize("fusion", FUSIONS)
 @pytest.mark.parametrize("mode,inner", [(0, 0), (1, 6), (1, 7), (1, 8)])
-def test_cg_converges_oracle_residual(setup, mode, inner, unfused):
+def test_cg_converges_oracle_residual(setup, mode, inner, fusion):
     fem, dev, bt, bo, A = setup
     rtol = 1e-8
-    rep, x = solve(setup, mode, inner, rtol, unfused=unfused, history=64)
+    rep, x = solve(setup, mode, inner, rtol, fusion=fusion, history=64)
     hist = rep.pop("history")
     assert len(hist) == rep["reliable_updates"] + 1 and abs(hist[-1] - rep["rel_res"]) < 1e-20
     print(f"mode={mode} inner={inner}: {rep}")
@@ -73,13 +76,13 @@ def test_cg_converges_oracle_residual(setup, mode, inner, unfused):
     assert res <= 1.1 * rtol, res
 
 
-@pytest.mark.parametrize("unfused", [False, True])
-def test_fp64_iterations_match_oracle_cg(setup, unfused):
+@pytest.mark.parametrize("fusion", FUSIONS)
+def test_fp64_iterations_match_oracle_cg(setup, fusion):
     """Same recurrences in exact arithmetic: the GPU FP64 CG needs about as many
     iterations as the oracle's textbook CG for the same tolerance."""
     fem, dev, bt, bo, A = setup
     rtol = 1e-6
-    rep, x = solve(setup, 0, 0, rtol, unfused=unfused)
+    rep, x = solve(setup, 0, 0, rtol, fusion=fusion)
     _, it, _ = cg(A, bo, rtol=rtol)
     assert abs(rep["iters"] - it) <= max(3, 0.1 * it), (rep["iters"], it)
 
