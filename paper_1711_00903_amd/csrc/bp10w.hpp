@@ -64,6 +64,17 @@ __global__ __launch_bounds__(kWave) void bp10w_kernel(
     __shared__ TC sub[SU > SB ? SU : SB];
     __shared__ TC sa[NQ * NQ * PG];   // T[k][j][a], then W[k][j][a]
     TC *const su = sub, *const sb = sub;
+    // Scaled Jacobians narrower than FP64: the element's Ng^3 contiguous values
+    // are fetched as whole dwords by every lane (coalesced) and staged in LDS,
+    // instead of 2 Ng strided 2- or 4-byte loads per lane.  The dwords
+    // [d0, d1) are those wholly inside the element's block plus, for 16-bit
+    // values with an odd first index, the half-filled first one; a last value
+    // that shares its dword with the next element is fetched on its own.
+    constexpr bool WST = sizeof(TG) < 8;
+    constexpr int VPD = WST ? 4 / static_cast<int>(sizeof(TG)) : 1;   // values per dword
+    constexpr int NDW = WST ? NPG / VPD + 1 : 1;
+    constexpr int DPL = (NDW + kWave - 1) / kWave;                     // dword loads per lane
+    __shared__ uint32_t s_wd[NDW];
 
     const int L = threadIdx.x;
     if constexpr (SI) stage_table(s_I, I1d, NG * NQ);
@@ -92,11 +103,13 @@ __global__ __launch_bounds__(kWave) void bp10w_kernel(
         const int64_t base = e * NP + (gll ? L : 0);
 #pragma unroll
         for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
-        const TG *wJe = wJ + e * NPG;
+        if constexpr (!WST) {
+            const TG *wJe = wJ + e * NPG;
 #pragma unroll
-        for (int cq = 0; cq < NG / W; ++cq) {
-            if (p2) ld_stream_vec<W>(wJe + c0 * W + cq * NCG * W, wj0 + cq * W);
-            if (two) ld_stream_vec<W>(wJe + c1 * W + cq * NCG * W, wj1 + cq * W);
+            for (int cq = 0; cq < NG / W; ++cq) {
+                if (p2) ld_stream_vec<W>(wJe + c0 * W + cq * NCG * W, wj0 + cq * W);
+                if (two) ld_stream_vec<W>(wJe + c1 * W + cq * NCG * W, wj1 + cq * W);
+            }
         }
     };
     // One element per workgroup, no loop: a loop over elements would keep the
@@ -105,6 +118,21 @@ __global__ __launch_bounds__(kWave) void bp10w_kernel(
         const int64_t e = e0 + blockIdx.x;
         TC uc[NQ], wj0[NG], wj1[NG];
         request(e, uc, wj0, wj1);
+        const int64_t v0 = e * NPG;                     // first wJ value of the element
+        const int64_t d0 = v0 / VPD, nd = (v0 + NPG) / VPD - d0;
+        const int off = static_cast<int>(v0 - d0 * VPD);   // its index inside the staged dwords
+        uint32_t wst[WST ? DPL : 1];
+        uint16_t wlast = 0;
+        const bool tail = WST && VPD == 2 && ((v0 + NPG) % 2) == 1;
+        if constexpr (WST) {
+            const uint32_t *wd = reinterpret_cast<const uint32_t *>(wJ) + d0;
+#pragma unroll
+            for (int q = 0; q < DPL; ++q) {
+                const int t = L + q * kWave;
+                wst[q] = t < nd ? __builtin_nontemporal_load(wd + t) : 0u;
+            }
+            if (tail && L == 0) wlast = reinterpret_cast<const uint16_t *>(wJ)[v0 + NPG - 1];
+        }
         if (gll) {
             const int i = L % NQ, j = L / NQ;
 #pragma unroll
@@ -137,10 +165,26 @@ __global__ __launch_bounds__(kWave) void bp10w_kernel(
                 if (a != NG - 1 - a) sa[k * NQ * PG + jj * PG + NG - 1 - a] = ev - od;
             }
         }
+        if constexpr (WST) {
+#pragma unroll
+            for (int q = 0; q < DPL; ++q) {
+                const int t = L + q * kWave;
+                if (t < nd) s_wd[t] = wst[q];
+            }
+            if (tail && L == 0) reinterpret_cast<uint16_t *>(s_wd)[off + NPG - 1] = wlast;
+        }
         __syncthreads();
 
         // s-interpolation of columns (a2, b2) and (a2, Ng-1-b2), then the t-direction of each
         if (p2) {
+            if constexpr (WST) {
+                const TG *sw = reinterpret_cast<const TG *>(s_wd) + off;
+#pragma unroll
+                for (int c = 0; c < NG; ++c) {
+                    wj0[c] = to_compute(sw[c0 + c * NCG], TC{});
+                    wj1[c] = two ? to_compute(sw[c1 + c * NCG], TC{}) : TC(0);
+                }
+            }
             TC Tp[NQ], Tm[NQ];
             {
                 TC ie[HQ], io[QE > 0 ? QE : 1];

@@ -48,6 +48,15 @@ __device__ __forceinline__ TC uniform_entry(const double *__restrict__ g, const 
     else return s[idx];
 }
 
+// The same, with the source chosen by the caller: SCALAR reads the FP64 table
+// through the scalar cache, otherwise the LDS copy (broadcast reads).
+template <bool SCALAR, class TC>
+__device__ __forceinline__ TC table_entry(const double *__restrict__ g, const TC *s, int idx)
+{
+    if constexpr (SCALAR) return g[idx];
+    else return s[idx];
+}
+
 // Stage the fields of a group of `nvalid` consecutive elements (contiguous in
 // global memory) into LDS as [slot][k][j][i] with row length PQ.  Every thread
 // issues all of its loads before its first LDS store, so the group's loads are
@@ -102,6 +111,11 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     // longer fit in registers and each slab's factors are loaded as needed.
     constexpr bool PREF = NQ <= 10;
     constexpr int W = geo_vec(NQ, sizeof(TG));   // slabs per vector load of geometric data
+    // Uniform table entries of the t-direction: with FP64 arithmetic on FP64
+    // data through the scalar cache (the measured faster choice there); with
+    // narrower geometric data the packed factors leave VGPRs free and the LDS
+    // copy is faster than the SGPR spills the scalar entries cause.
+    constexpr bool SCALAR_TAB = std::is_same<TC, double>::value && std::is_same<TG, double>::value;
 
     __shared__ TC s_D[NQ * NQ];
     __shared__ TC s_u[EPB * VOL];
@@ -155,17 +169,18 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
         }
         const TG *Ge = G + (ok ? e : 0) * (6 * NP) + col * W;
-        TC gp[PREF ? 6 * NQ : 1];   // gp[f * NQ + k]: factor f at slab k
+        constexpr int NV = NQ / W;   // vectors per factor and column
+        // gp[f * NV + k / W], lane k % W: factor f at slab k, stored precision
+        packed_vec<W, TG> gp[PREF ? 6 * NV : 1];
         if constexpr (PREF) {
             if (ok) {
 #pragma unroll
                 for (int f = 0; f < 6; ++f)
 #pragma unroll
-                    for (int kq = 0; kq < NQ / W; ++kq)
-                        ld_stream_vec<W>(Ge + f * NP + kq * NC * W, gp + f * NQ + kq * W);
+                    for (int kq = 0; kq < NV; ++kq) gp[f * NV + kq].stream(Ge + f * NP + kq * NC * W);
             } else {
 #pragma unroll
-                for (int x = 0; x < 6 * NQ; ++x) gp[x] = TC(0);
+                for (int x = 0; x < 6 * NV; ++x) gp[x].zero();
             }
         }
         TC gw[PREF ? 1 : 6 * W];    // non-prefetched: the factors of W slabs at a time
@@ -185,16 +200,16 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             for (int m = 0; m < NQ; ++m) {
                 qr += Di[m] * row[m];
                 qs += Dj[m] * cln[m * P];
-                qt += uniform_entry(D1d, s_D, k * NQ + m) * uc[m];
+                qt += table_entry<SCALAR_TAB>(D1d, s_D, k * NQ + m) * uc[m];
             }
             TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
             if constexpr (PREF) {
-                grr = gp[0 * NQ + k];
-                grs = gp[1 * NQ + k];
-                grt = gp[2 * NQ + k];
-                gss = gp[3 * NQ + k];
-                gst = gp[4 * NQ + k];
-                gtt = gp[5 * NQ + k];
+                grr = gp[0 * NV + k / W].template get<TC>(k % W);
+                grs = gp[1 * NV + k / W].template get<TC>(k % W);
+                grt = gp[2 * NV + k / W].template get<TC>(k % W);
+                gss = gp[3 * NV + k / W].template get<TC>(k % W);
+                gst = gp[4 * NV + k / W].template get<TC>(k % W);
+                gtt = gp[5 * NV + k / W].template get<TC>(k % W);
             } else if (ok) {
                 if (k % W == 0) {
 #pragma unroll
@@ -226,7 +241,7 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             for (int m = 0; m < NQ; ++m) {
                 acc += DiT[m] * rrow[m];
                 acc += DjT[m] * scol[m * P];
-                acc += uniform_entry(D1d, s_D, m * NQ + k) * wt[m];
+                acc += table_entry<SCALAR_TAB>(D1d, s_D, m * NQ + k) * wt[m];
             }
             if (ok) {
                 const int64_t idx = base + k * NC;

@@ -415,6 +415,11 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     const double delta = opt->delta > 0 ? opt->delta : 0.1;
     const int every = opt->check_every > 0 ? opt->check_every : 1;
     bool converged = rmax <= target || bnorm == 0.0;
+    // A recursive residual below the target triggers a true-residual check;
+    // when that check fails (the true residual sits at its rounding floor while
+    // the recursion keeps falling), the next such check waits until the
+    // recursive residual has halved again, so checks do not repeat every step.
+    double check_at = target;
     int it = 0;
     while (!converged && it < opt->max_iters) {
         ++it;
@@ -423,7 +428,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
             if (apply_cgop(c, prec_lo, reinterpret_cast<const double *>(rl), reinterpret_cast<double *>(p),
                            &sc->beta, it > 1, reinterpret_cast<double *>(Ap), partg) != hipSuccess)
                 return FEM_ERR_HIP;
-            fin(partg, groups, &sc->pAp, FIN_ALPHA);
+            fin(partg, cgop_groups(op->N, op->E), &sc->pAp, FIN_ALPHA);
         } else if (split) {
             if (apply_A_split(c, prec_lo, it > 1 ? reinterpret_cast<const double *>(rl) : nullptr, &sc->beta,
                               reinterpret_cast<double *>(p), reinterpret_cast<double *>(Ap), partg) != hipSuccess)
@@ -445,7 +450,8 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                 break;
             }
             const double rn = std::sqrt(h.rr_new);
-            if (rn < delta * rmax || rn <= target) {
+            if (rn < delta * rmax || rn <= check_at) {
+                const bool by_target = !(rn < delta * rmax);
                 // reliable update: fold the low-precision iterate into x and
                 // replace the recursive residual by the true one
                 hipLaunchKernelGGL(merge_kernel<TV>, G, B, 0, s, x, xl, n);
@@ -460,6 +466,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                     converged = true;
                     break;
                 }
+                check_at = by_target ? 0.5 * rn : target;
             }
         }
         // beta = rr_new / rr; rr = rr_new (the direction update itself is

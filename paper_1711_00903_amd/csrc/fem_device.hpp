@@ -107,6 +107,25 @@ template <> struct raw_vec<8> { typedef unsigned int type __attribute__((ext_vec
 template <> struct raw_vec<4> { typedef unsigned int type; };
 template <> struct raw_vec<2> { typedef unsigned short type; };
 
+// One aligned vector of W stored values, kept packed in registers (a 16-bit
+// or FP32 value takes a half or one VGPR instead of the two of its FP64
+// widening) and widened to the compute type only when used.
+template <int W, class TS> struct packed_vec {
+    using R = typename raw_vec<W * sizeof(TS)>::type;
+    R v;
+    __device__ __forceinline__ void stream(const TS *__restrict__ p)
+    {
+        v = __builtin_nontemporal_load(reinterpret_cast<const R *>(p));
+    }
+    __device__ __forceinline__ void zero() { v = R{}; }
+    template <class TC> __device__ __forceinline__ TC get(int r) const
+    {
+        TS tmp[W];
+        __builtin_memcpy(tmp, &v, sizeof(R));
+        return to_compute(tmp[r], TC{});
+    }
+};
+
 // W consecutive stored values (one aligned vector), streamed non-temporally and
 // converted to the compute type.
 template <int W, class TC, class TS>

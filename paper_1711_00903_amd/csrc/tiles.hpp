@@ -44,13 +44,14 @@ constexpr bool bp30_glds(int nq, int epb, int cbytes, int gbytes)
 // even-odd kernel (bp10w.hpp).
 constexpr bool bp10_wave(int nq, int epb) { return epb == 1 && nq <= 8; }
 
-constexpr int bp10w_lds_bytes(int nq, int bytes)
+constexpr int bp10w_lds_bytes(int nq, int bytes, int gbytes)
 {
     const int ng = nq + 1, hg = (ng + 1) / 2, hq = (nq + 1) / 2;
     const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
     const int su = nq * nq * pq, sb = nq * ng * pg;
     const int full = bytes == 8 ? 1 : ng * nq;   // FP64 reads the full table from global memory
-    return (4 * hg * hq + full + (su > sb ? su : sb) + nq * nq * pg) * bytes;
+    const int wst = gbytes < 8 ? (ng * ng * ng / (4 / gbytes) + 1) * 4 : 4;   // staged scaled Jacobians
+    return (4 * hg * hq + full + (su > sb ? su : sb) + nq * nq * pg) * bytes + wst;
 }
 
 // LDS bytes of one workgroup for values of `bytes` bytes (tables included);
@@ -59,7 +60,7 @@ constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
 {
     const int ng = nq + 1;
     const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
-    if (op == 0 && bp10_wave(nq, epb)) return bp10w_lds_bytes(nq, bytes);
+    if (op == 0 && bp10_wave(nq, epb)) return bp10w_lds_bytes(nq, bytes, gbytes);
     if (op == 1) return (nq * nq + 3 * epb * nq * nq * pq) * bytes;
     if (op == 0) {
         const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
