@@ -109,9 +109,27 @@ __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl
 {
     __shared__ double sh[kRedThreads];
     const TV alpha = static_cast<TV>(sc->alpha);
+    // pairs of entries per access (8- or 16-byte vectors), then the odd last entry
+    using V2 = TV __attribute__((ext_vector_type(2)));
+    const int64_t n2 = n / 2;
+    V2 *x2 = reinterpret_cast<V2 *>(xl);
+    V2 *r2 = reinterpret_cast<V2 *>(rl);
+    const V2 *p2 = reinterpret_cast<const V2 *>(p);
+    const V2 *a2 = reinterpret_cast<const V2 *>(Ap);
     double s = 0;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n2;
          i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+        const V2 pv = p2[i], av = a2[i];
+        V2 xv = x2[i], rv = r2[i];
+        xv += alpha * pv;
+        rv -= alpha * av;
+        x2[i] = xv;
+        r2[i] = rv;
+        s += static_cast<double>(rv.x) * static_cast<double>(rv.x);
+        s += static_cast<double>(rv.y) * static_cast<double>(rv.y);
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t i = n - 1;
         xl[i] += alpha * p[i];
         const TV r = rl[i] - alpha * Ap[i];
         rl[i] = r;
