@@ -230,6 +230,71 @@ def run_sweep(args) -> int:
     return 0
 
 
+def run_batch(args) -> int:
+    """Ragged batch: 64 independent meshes (N ~ U{1..15}, E log-uniform in
+    [64, 32768], operator uniform over BP1.0 / BP3.5 / BP3.0; seed 355), FP64
+    and FP32 storage.  Times one eager enqueue of all applies on one stream
+    (fem_batch_apply) against one replay of the captured graph
+    (fem_batch_graph_*) with 1, 4 and 8 lanes, each with the tuned packing of
+    its (operator, N, precision)."""
+    import torch
+
+    import workloads
+    from paper_1711_00903_amd import fem, tune
+    from paper_1711_00903_amd.mesh import DeviceMesh, FIELD_DTYPE, out_dtype
+
+    fem.lib()
+    spec = workloads.ragged_batch(args.batch_count)
+    stream = torch.cuda.Stream()   # graph capture needs a stream other than the legacy default one
+    devs = []
+    for m in spec:
+        X = workloads.element_vertices(m.n, E=m.E, seed=m.mesh_seed)
+        devs.append(DeviceMesh(m.N, X, h=1.0 / m.n))
+    out = {"workload": f"ragged_batch_{len(spec)}",
+           "meshes": [dict(op=m.op, N=m.N, E=m.E) for m in spec], "precs": {}}
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            fn()
+        t1.record(stream)
+        t1.synchronize()
+        return t0.elapsed_time(t1) / reps
+
+    for pname in args.batch_precs.split(","):
+        prec = fem.PREC_NAMES[pname]
+        descs, keep = [], []
+        nbytes = dofs = 0
+        for m, dev in zip(spec, devs):
+            u = torch.from_numpy(workloads.field(m.E, m.N + 1, seed=m.field_seed)).cuda().to(FIELD_DTYPE[prec])
+            y = torch.zeros(u.shape, dtype=out_dtype(prec), device="cuda")
+            keep += [u, y]
+            descs.append(dev.desc(m.op, u, y, prec=prec))
+            nbytes += tune.alg_bytes(m.op, m.N, m.E, prec)
+            dofs += m.E * (m.N + 1) ** 3
+        torch.cuda.synchronize()
+        rec = {"alg_bytes": nbytes, "dofs": dofs}
+        rec["eager_ms"] = timed(lambda: fem.fem_batch_apply(descs, stream), args.batch_reps)
+        for lanes in (1, 4, 8):
+            g = fem.BatchGraph(descs, lanes=lanes, stream=stream)
+            rec[f"graph{lanes}_ms"] = timed(lambda: g.launch(stream), args.batch_reps)
+            g.destroy()
+        best = min(rec[k] for k in rec if k.endswith("_ms"))
+        rec["best_GB/s"] = nbytes / (best * 1e-3) / 1e9
+        rec["best_GDOF/s"] = dofs / (best * 1e-3) / 1e9
+        rec["graph_speedup"] = rec["eager_ms"] / min(rec["graph1_ms"], rec["graph4_ms"], rec["graph8_ms"])
+        log(f"batch {pname}: {rec}")
+        out["precs"][pname] = rec
+        del descs, keep
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,9 +321,15 @@ def main() -> int:
     ap.add_argument("--sweep-ops", default="BP10,BP35,BP30")
     ap.add_argument("--sweep-reps", type=int, default=10)
     ap.add_argument("--tune-out", default="")
+    ap.add_argument("--batch", action="store_true", help="ragged batch: eager vs captured graph")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-precs", default="f64,f32")
+    ap.add_argument("--batch-reps", type=int, default=10)
     args = ap.parse_args()
     if args.sweep:
         return run_sweep(args)
+    if args.batch:
+        return run_batch(args)
     if args.cg:
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)

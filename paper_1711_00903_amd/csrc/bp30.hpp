@@ -17,8 +17,15 @@
 
 namespace fem {
 
+// Minimum waves per SIMD asked of the register allocator.  At Nq = 8 (and
+// Nq = 6 with one element per workgroup) the kernel then fits 256 VGPRs without
+// spills and runs two waves per SIMD instead of one (4.0 instead of 5.7 ms at
+// N = 7, E = 262144); elsewhere the cap would spill, so it is not set.
+constexpr int bp30_min_waves(int nq, int epb) { return (nq == 8 || (nq == 6 && epb == 1)) ? 2 : 1; }
+
 template <int NQ, int EPB, class TG, class TV>
-__global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
+__global__ __launch_bounds__(threads_for(2, NQ, EPB))
+__attribute__((amdgpu_waves_per_eu(bp30_min_waves(NQ, EPB)))) void bp30_kernel(
     int64_t E, int64_t ngroups, const double *__restrict__ I1d, const double *__restrict__ Dgl,
     const TG *__restrict__ G, const TG *__restrict__ wJ, typename compute_pair<TG, TV>::type lambda,
     const TV *__restrict__ u, typename output_of<TV>::type *__restrict__ y,
@@ -38,18 +45,12 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
     constexpr int R2 = R2a > R2b ? R2a : R2b;
     constexpr int SLOT = bp30_slot_values(NQ, sizeof(TC));
     static_assert(SLOT == R1 + R2 + NG * NG * PG, "LDS slot layout");
-    // the element's 6 Ng^3 geometric factors go to LDS by direct loads at the
-    // start of each element (when they fit): all of its G traffic is in flight
-    // from the first instruction on, without holding registers
-    constexpr bool GLDS = bp30_glds(NQ, EPB, sizeof(TC), sizeof(TG));
-    constexpr int NT = threads_for(2, NQ, EPB);
     constexpr bool TREG = NQ <= 6;
     constexpr int W = geo_vec(NG, sizeof(TG));   // Gauss slabs per vector load of G / wJ
 
     __shared__ TC s_I[NG * NQ];
     __shared__ TC s_D[NG * NG];
     __shared__ TC s_w[EPB * SLOT];
-    __shared__ __align__(16) TG s_g[GLDS ? 6 * NPG : 1];
 
     const int t = threadIdx.x;
     const int slot = t / NCG;
@@ -84,8 +85,6 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
 
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t e0 = g * EPB;
-        // (with GLDS, EPB == 1 and e0 < E: the group's one element is valid)
-        if constexpr (GLDS) lds_dma<6 * NPG * sizeof(TG), NT>(s_g, G + e0 * (6 * NPG));
         {
             const int nvalid = static_cast<int>((E - e0) < EPB ? (E - e0) : EPB);
             stage_fields<NQ, EPB, threads_for(2, NQ, EPB), SLOT, PQ>(s_w, u + e0 * NP, nvalid);
@@ -149,15 +148,7 @@ __global__ __launch_bounds__(threads_for(2, NQ, EPB)) void bp30_kernel(
                 qt += uniform_entry(Dgl, s_D, c * NG + m) * qg[m];
             }
             TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
-            if constexpr (GLDS) {
-                const int64_t o = geo_offset(col, c, NG, W);
-                grr = to_compute(s_g[0 * NPG + o], TC{});
-                grs = to_compute(s_g[1 * NPG + o], TC{});
-                grt = to_compute(s_g[2 * NPG + o], TC{});
-                gss = to_compute(s_g[3 * NPG + o], TC{});
-                gst = to_compute(s_g[4 * NPG + o], TC{});
-                gtt = to_compute(s_g[5 * NPG + o], TC{});
-            } else if (ok) {
+            if (ok) {
                 if (c % W == 0) {
 #pragma unroll
                     for (int f = 0; f < 6; ++f) ld_stream_vec<W>(Ge + f * NPG + (c / W) * NCG * W, gw + f * W);

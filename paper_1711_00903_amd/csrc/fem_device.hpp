@@ -10,11 +10,11 @@
 namespace fem {
 
 constexpr int kWave = 64;
-constexpr int kWaveDma = kWave;
 
 // ---------------------------------------------------------------------------
-// Storage types.  u, G and wJ are stored in one of four precisions; FP64
-// storage computes in FP64, the others in FP32.
+// Storage types.  Fields (u, y) are FP64, FP32, BF16 or FP16, and geometric
+// data (G, wJ) FP64, FP32, BF16 or FP16; the arithmetic type follows from the
+// pair (compute_pair below).
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 using f16_t = _Float16;
@@ -137,37 +137,6 @@ __device__ __forceinline__ void ld_stream_vec(const TS *__restrict__ p, TC *out)
     __builtin_memcpy(tmp, &v, sizeof(R));
 #pragma unroll
     for (int r = 0; r < W; ++r) out[r] = to_compute(tmp[r], TC{});
-}
-
-// ---------------------------------------------------------------------------
-// Direct global -> LDS copy (gfx950 LDS DMA): `bytes` contiguous bytes from
-// `src` to `dst`, issued by all `nt` threads of the workgroup in 16-byte (or,
-// when the block or its alignment does not allow it, 4-byte) pieces.  The data
-// never passes through registers; it is complete after the next workgroup
-// barrier (the compiler waits for the outstanding loads before the barrier).
-// The LDS address of each instruction is wave-uniform: lane l of the wave
-// writes piece (wave base + l).
-// ---------------------------------------------------------------------------
-template <int BYTES, int NT>
-__device__ __forceinline__ void lds_dma(void *dst, const void *src)
-{
-    constexpr int CH = (BYTES % 16 == 0) ? 16 : 4;
-    static_assert(BYTES % 4 == 0, "LDS DMA moves whole dwords");
-    constexpr int NCH = BYTES / CH;
-    const int lane = threadIdx.x & (kWaveDma - 1);
-    const int wave0 = threadIdx.x - lane;
-#pragma unroll
-    for (int s = 0; s < (NCH + NT - 1) / NT; ++s) {
-        const int x = static_cast<int>(threadIdx.x) + s * NT;
-        if (x < NCH) {
-            auto *d = reinterpret_cast<__attribute__((address_space(3))) char *>(
-                reinterpret_cast<uintptr_t>(dst) + static_cast<uintptr_t>(wave0 + s * NT) * CH);
-            const char *g = static_cast<const char *>(src) + static_cast<int64_t>(x) * CH;
-            auto *l = reinterpret_cast<__attribute__((address_space(3))) void *>(d);
-            if constexpr (CH == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
-            else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------

@@ -19,9 +19,7 @@ constexpr int kMaxLds = 160 * 1024;   // gfx950 LDS per workgroup
 
 constexpr int columns(int op, int nq) { return op == 1 ? nq * nq : (nq + 1) * (nq + 1); }
 
-// BP3.0 stages each element's geometric factors (6 Ng^3 values of `gbytes`
-// bytes) in LDS by direct global -> LDS loads when one element per workgroup
-// fits in 96 KiB with them (two workgroups per CU).
+// LDS values of one BP3.0 element slot (three regions reused across phases).
 constexpr int bp30_slot_values(int nq, int bytes)
 {
     const int ng = nq + 1;
@@ -31,13 +29,6 @@ constexpr int bp30_slot_values(int nq, int bytes)
     const int r2a = nq * nq * pg, r2b = ng * ng * pg;
     const int r2 = r2a > r2b ? r2a : r2b;
     return r1 + r2 + ng * ng * pg;
-}
-
-constexpr bool bp30_glds(int nq, int epb, int cbytes, int gbytes)
-{
-    const int ng = nq + 1;
-    const int gb = 6 * ng * ng * ng * gbytes;
-    return epb == 1 && gb % 4 == 0 && bp30_slot_values(nq, cbytes) * cbytes + gb <= 96 * 1024;
 }
 
 // BP1.0 with one element per workgroup and Nq <= 8 runs the one-wave
@@ -55,7 +46,7 @@ constexpr int bp10w_lds_bytes(int nq, int bytes, int gbytes)
 }
 
 // LDS bytes of one workgroup for values of `bytes` bytes (tables included);
-// gbytes: stored size of a geometric value (BP3.0 LDS staging).
+// gbytes: stored size of a geometric value (BP1.0 one-wave staging).
 constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
 {
     const int ng = nq + 1;
@@ -66,8 +57,7 @@ constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
         const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
         return (ng * nq + epb * slot) * bytes;
     }
-    const int gstage = bp30_glds(nq, epb, bytes, gbytes) ? 6 * ng * ng * ng * gbytes : 0;
-    return (ng * nq + ng * ng + epb * bp30_slot_values(nq, bytes)) * bytes + gstage;
+    return (ng * nq + ng * ng + epb * bp30_slot_values(nq, bytes)) * bytes;
 }
 
 constexpr int threads_for(int op, int nq, int epb)
