@@ -120,7 +120,7 @@ CG_ARMS = [("fp64", 0, 0), ("f32g64", 1, 6), ("bf16g64", 1, 7), ("f16g64", 1, 8)
 
 
 def run_cg(args) -> int:
-    """Time to solution of (S + M) x = b, N = 7, 64^3 elements (134M local DOFs):
+    """Time to solution of (S + lambda M) x = b, N = 7, 64^3 elements (134M local DOFs):
     FP64 CG against mixed precision (reduced-precision geometric data), all with
     FP64 reliable updates and the same stopping rule on the FP64 true residual."""
     import math
@@ -154,14 +154,14 @@ def run_cg(args) -> int:
             dev.geometry(fem.FEM_QUAD_GLL, prec, want_wJ=False)
             dev.geometry(fem.FEM_QUAD_GL, prec, want_G=False, kind="wJ")
     torch.cuda.synchronize()
-    out = {"workload": f"cg_n7_e{E}", "E": E, "N": Ncg, "dofs": E * (Ncg + 1) ** 3, "lambda": 1.0,
+    out = {"workload": f"cg_n7_e{E}", "E": E, "N": Ncg, "dofs": E * (Ncg + 1) ** 3, "lambda": args.cg_lambda,
            "fusion": args.cg_fusion, "arms": {}}
     tau = args.cg_rtol
     if args.cg_floor_iters > 0:
         # attainable FP64 accuracy: run FP64 CG far past convergence and take the
         # median true residual over the second half of its reliable updates
         x = torch.zeros_like(b)
-        rep = dev.cg_solve(b, x, lam=1.0, mode=0, rtol=1e-16, max_iters=args.cg_floor_iters,
+        rep = dev.cg_solve(b, x, lam=args.cg_lambda, mode=0, rtol=1e-16, max_iters=args.cg_floor_iters,
                            fusion=fem.FUSION_NAMES[args.cg_fusion], history=4096)
         hist = rep.pop("history")
         floor = min(hist)
@@ -174,7 +174,7 @@ def run_cg(args) -> int:
     for name, mode, prec in arms:
         x = torch.zeros_like(b)
         maxit = args.cg_max_iters if name != "f32" else min(args.cg_max_iters, 4000)
-        rep = dev.cg_solve(b, x, lam=1.0, mode=mode, inner_prec=prec, rtol=tau, max_iters=maxit,
+        rep = dev.cg_solve(b, x, lam=args.cg_lambda, mode=mode, inner_prec=prec, rtol=tau, max_iters=maxit,
                            fusion=fem.FUSION_NAMES[args.cg_fusion])
         log(f"cg: {name}: {rep}")
         rec = dict(rep)
@@ -188,7 +188,7 @@ def run_cg(args) -> int:
             bo = (np.sin(np.pi * xo[..., 0]) * np.sin(np.pi * xo[..., 1]) * np.sin(np.pi * xo[..., 2])
                   + 1e-3 * workloads.rhs_noise(E, Ncg + 1))
             del xo
-            rec["oracle_rel_res"] = true_relative_residual(lambda v: pb.cg_operator(v, 1.0), bo,
+            rec["oracle_rel_res"] = true_relative_residual(lambda v: pb.cg_operator(v, args.cg_lambda), bo,
                                                            x.cpu().numpy())
             log(f"cg: {name}: oracle residual {rec['oracle_rel_res']:.3e}")
         out["arms"][name] = rec
@@ -307,6 +307,8 @@ def main() -> int:
     ap.add_argument("--cg", action="store_true", help="time the CG workload instead")
     ap.add_argument("--cg-grid", type=int, default=64)
     ap.add_argument("--cg-rtol", type=float, default=1e-10)
+    ap.add_argument("--cg-lambda", type=float, default=1.0,
+                    help="mass coefficient of A = S + lambda M (1/h^2 = 4096 makes 1e-10 attainable in FP64)")
     ap.add_argument("--cg-floor-iters", type=int, default=0,
                     help="first run FP64 CG this long and set the tolerance to max(rtol, 2 x floor)")
     ap.add_argument("--cg-max-iters", type=int, default=20000)
