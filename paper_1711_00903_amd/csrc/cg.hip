@@ -99,7 +99,21 @@ __global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double *__r
     }
 }
 
-// x_lo += alpha p; r_lo -= alpha Ap; partial sums of r_lo . r_lo
+// x_lo += alpha p; r_lo -= alpha Ap; per-block partial sums of r_lo . r_lo.
+// Non-persistent: block b owns kUpdPairs * kRedThreads consecutive pairs of
+// entries (16-byte vectors for FP64), every thread issues all its loads before
+// its first store (the streaming-copy pattern; a grid-stride loop over the
+// same data reaches only 4.7 TB/s).  The odd last entry goes to the last
+// block's thread 0.
+constexpr int kUpdPairs = 4;
+constexpr int64_t kUpdBlockPairs = static_cast<int64_t>(kUpdPairs) * kRedThreads;
+
+inline int64_t update_blocks(int64_t n)
+{
+    const int64_t b = (n / 2 + kUpdBlockPairs - 1) / kUpdBlockPairs;
+    return b > 0 ? b : 1;
+}
+
 template <class TV>
 __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl, TV *__restrict__ rl,
                                                              const TV *__restrict__ p,
@@ -109,26 +123,38 @@ __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl
 {
     __shared__ double sh[kRedThreads];
     const TV alpha = static_cast<TV>(sc->alpha);
-    // pairs of entries per access (8- or 16-byte vectors), then the odd last entry
     using V2 = TV __attribute__((ext_vector_type(2)));
     const int64_t n2 = n / 2;
     V2 *x2 = reinterpret_cast<V2 *>(xl);
     V2 *r2 = reinterpret_cast<V2 *>(rl);
     const V2 *p2 = reinterpret_cast<const V2 *>(p);
     const V2 *a2 = reinterpret_cast<const V2 *>(Ap);
-    double s = 0;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n2;
-         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
-        const V2 pv = p2[i], av = a2[i];
-        V2 xv = x2[i], rv = r2[i];
-        xv += alpha * pv;
-        rv -= alpha * av;
-        x2[i] = xv;
-        r2[i] = rv;
-        s += static_cast<double>(rv.x) * static_cast<double>(rv.x);
-        s += static_cast<double>(rv.y) * static_cast<double>(rv.y);
+    const int64_t i0 = blockIdx.x * kUpdBlockPairs + threadIdx.x;
+    V2 pv[kUpdPairs], av[kUpdPairs], xv[kUpdPairs], rv[kUpdPairs];
+#pragma unroll
+    for (int q = 0; q < kUpdPairs; ++q) {
+        const int64_t i = i0 + q * kRedThreads;
+        if (i < n2) {
+            pv[q] = p2[i];
+            av[q] = a2[i];
+            xv[q] = x2[i];
+            rv[q] = r2[i];
+        }
     }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0;
+#pragma unroll
+    for (int q = 0; q < kUpdPairs; ++q) {
+        const int64_t i = i0 + q * kRedThreads;
+        if (i < n2) {
+            xv[q] += alpha * pv[q];
+            rv[q] -= alpha * av[q];
+            x2[i] = xv[q];
+            r2[i] = rv[q];
+            s += static_cast<double>(rv[q].x) * static_cast<double>(rv[q].x);
+            s += static_cast<double>(rv[q].y) * static_cast<double>(rv[q].y);
+        }
+    }
+    if ((n & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         const int64_t i = n - 1;
         xl[i] += alpha * p[i];
         const TV r = rl[i] - alpha * Ap[i];
@@ -213,8 +239,11 @@ size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 // one-pass operator, one per element of the two-kernel form.
 int64_t cg_groups(int N, int64_t E)
 {
-    const int64_t g = cgop_groups(N, E);
-    return g > E ? g : E;
+    const int64_t n = E * static_cast<int64_t>(N + 1) * (N + 1) * (N + 1);
+    int64_t g = cgop_groups(N, E);
+    if (E > g) g = E;
+    if (update_blocks(n) > g) g = update_blocks(n);
+    return g;
 }
 
 struct Layout {
@@ -459,7 +488,9 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
             hipLaunchKernelGGL((dot_kernel<TV, TV>), G, B, 0, s, p, Ap, n, part);
             fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
         }
-        hipLaunchKernelGGL(update_kernel<TV>, G, B, 0, s, xl, rl, p, Ap, n, sc, part2);
+        hipLaunchKernelGGL(update_kernel<TV>, dim3(static_cast<unsigned>(update_blocks(n))), B, 0, s, xl, rl, p,
+                           Ap, n, sc, partg);
+        hipLaunchKernelGGL(sum_kernel, G, B, 0, s, partg, update_blocks(n), part2);
         fin(part2, kRedBlocks, &sc->rr_new, FIN_PLAIN);
         if (it % every == 0 || it == opt->max_iters) {
             if (!fetch()) return FEM_ERR_HIP;
