@@ -14,7 +14,7 @@
 #pragma once
 
 #include "bp35.hpp"
-#include "bp10w.hpp"
+#include "bp10t.hpp"
 
 namespace fem {
 
@@ -198,7 +198,7 @@ hipError_t bp10_launch_nq(const ApplyArgs &a, hipStream_t s)
     constexpr auto ch = epb_choices(0, NQ);
     const int epb = a.epb > 0 ? a.epb : epb_default(0, NQ);
     if (epb == ch[0]) {
-        if constexpr (bp10_wave(NQ, ch[0])) return bp10w_launch_t<NQ, TG, TV>(a, s);
+        if constexpr (bp10_wave(NQ, ch[0])) return bp10t_launch_t<NQ, TG, TV>(a, s);
         else return bp10_launch_t<NQ, ch[0], TG, TV>(a, s);
     }
     if constexpr (ch[1] > 0) if (epb == ch[1]) return bp10_launch_t<NQ, ch[1], TG, TV>(a, s);

@@ -1,0 +1,308 @@
+// bp10t.hpp -- BP1.0 mass operator, one wave64 per element (Nq <= 8), with
+// every one-direction contraction done by a lane that owns a whole line.
+//
+// The six contractions of Alg. 1-3 (interpolate t, s, r; scale by wJ; project
+// r, s, t) are each a small matrix times one line of the element.  Here a lane
+// holds the line in registers and produces all outputs of that line with the
+// uniform 1-D table, and the element is turned between line directions
+// through LDS (one write and one read per point), instead of every lane
+// reading a whole LDS line for each single output.  Each line product uses
+// the centro-symmetry I[a][i] = I[Ng-1-a][Nq-1-i] (the symmetry the BP1.0
+// optimisation section exploits) in even-odd form: with the half tables
+//     Ie[a][m] = (I[a][m] + I[a][Nq-1-m]) / 2   (a < ceil(Ng/2), m < ceil(Nq/2))
+//     Io[a][m] = (I[a][m] - I[a][Nq-1-m]) / 2   (a < floor(Ng/2), m < floor(Nq/2))
+// interpolation of a line x (Nq values) to Gauss points is
+//     y_a = e_a + o_a,  y_{Ng-1-a} = e_a - o_a,
+//     e_a = sum_m Ie[a][m] (x_m + x_{Nq-1-m}) [+ Ie[a][mid] x_mid],  o_a = sum_m Io[a][m] (x_m - x_{Nq-1-m}),
+// and projection (I^T) of a Gauss line v uses the same half tables with the
+// roles of the indices exchanged.
+//
+// Phases (N = 7: Nq = 8, Ng = 9; lines over one wave, the second pass of a
+// phase with more than 64 lines uses the first lanes again):
+//   t-interpolation  lanes (i,j): u column in registers -> A[c][j][i]          64 lines
+//   s-interpolation  lines (i,c): A[c][*][i]            -> B[c][b][i]          72 lines
+//   r-direction      lines (b,c): B[c][b][*] -> interpolate, x wJ, project -> B[c][b][*] (in place)   81 lines
+//   s-projection     lines (i,c): B[c][*][i]            -> A[c][j][i]          72 lines
+//   t-projection     lanes (i,j): A[*][j][i]            -> y[k][j][i]          64 lines
+// The element's scaled Jacobians (one contiguous block) are fetched by every
+// lane in coalesced pieces at the start and staged in A once the
+// s-interpolation has consumed it.
+#pragma once
+
+#include "bp35.hpp"
+
+namespace fem {
+
+// Interpolation of one line: x (NQ values) -> y (NG = NQ+1 values).
+template <int NQ, class TC>
+__device__ __forceinline__ void line_interp(const TC *x, TC *y, const TC (*Ie)[(NQ + 1) / 2],
+                                            const TC (*Io)[NQ / 2 > 0 ? NQ / 2 : 1])
+{
+    constexpr int NG = NQ + 1, QE = NQ / 2, GE = NG / 2, HG = (NG + 1) / 2;
+    TC xp[QE > 0 ? QE : 1], xm[QE > 0 ? QE : 1];
+#pragma unroll
+    for (int m = 0; m < QE; ++m) {
+        xp[m] = x[m] + x[NQ - 1 - m];
+        xm[m] = x[m] - x[NQ - 1 - m];
+    }
+#pragma unroll
+    for (int a = 0; a < HG; ++a) {
+        TC ev = 0, od = 0;
+#pragma unroll
+        for (int m = 0; m < QE; ++m) ev += Ie[a][m] * xp[m];
+        if constexpr (NQ % 2 == 1) ev += Ie[a][QE] * x[QE];
+        if (a < GE) {
+#pragma unroll
+            for (int m = 0; m < QE; ++m) od += Io[a][m] * xm[m];
+            y[a] = ev + od;
+            y[NG - 1 - a] = ev - od;
+        } else {
+            y[a] = ev;   // middle Gauss point (NG odd)
+        }
+    }
+}
+
+// Projection of one line: v (NG values) -> w (NQ values), w_i = sum_a I[a][i] v_a.
+template <int NQ, class TC>
+__device__ __forceinline__ void line_project(const TC *v, TC *w, const TC (*Ie)[(NQ + 1) / 2],
+                                             const TC (*Io)[NQ / 2 > 0 ? NQ / 2 : 1])
+{
+    constexpr int NG = NQ + 1, QE = NQ / 2, GE = NG / 2, HQ = (NQ + 1) / 2;
+    TC vp[GE > 0 ? GE : 1], vm[GE > 0 ? GE : 1];
+#pragma unroll
+    for (int a = 0; a < GE; ++a) {
+        vp[a] = v[a] + v[NG - 1 - a];
+        vm[a] = v[a] - v[NG - 1 - a];
+    }
+#pragma unroll
+    for (int i = 0; i < HQ; ++i) {
+        TC ev = 0, od = 0;
+#pragma unroll
+        for (int a = 0; a < GE; ++a) ev += Ie[a][i] * vp[a];
+        if constexpr (NG % 2 == 1) ev += Ie[GE][i] * v[GE];
+        if (i < QE) {
+#pragma unroll
+            for (int a = 0; a < GE; ++a) od += Io[a][i] * vm[a];
+            w[i] = ev + od;
+            w[NQ - 1 - i] = ev - od;
+        } else {
+            w[i] = ev;   // middle GLL point (NQ odd)
+        }
+    }
+}
+
+// DOT: also write part[e] = sum over the element's nodes of u * y (y the final
+// output), reduced across the wave in a fixed order.
+template <int NQ, class TG, class TV, bool DOT = false>
+__global__ __launch_bounds__(kWave) void bp10t_kernel(
+    int64_t E, const double *__restrict__ I1d, const TG *__restrict__ wJ, const TV *__restrict__ u,
+    typename output_of<TV>::type *__restrict__ y, typename compute_pair<TG, TV>::type beta,
+    typename compute_pair<TG, TV>::type oscale, double *__restrict__ part = nullptr, int64_t e0 = 0)
+{
+    using TC = typename compute_pair<TG, TV>::type;
+    using TY = typename output_of<TV>::type;
+    constexpr int NG = NQ + 1;
+    constexpr int NC = NQ * NQ;
+    constexpr int NP = NC * NQ;
+    constexpr int NPG = NG * NG * NG;
+    constexpr int HG = (NG + 1) / 2, HQ = (NQ + 1) / 2, GE = NG / 2, QE = NQ / 2;
+    constexpr int P = lds_row(NQ, sizeof(TC));   // row length of both LDS volumes (rows along i)
+    constexpr int SA = NQ * P;                   // slab of A: [j][i]
+    constexpr int SB = NG * P;                   // slab of B: [b][i]
+    constexpr int W = geo_vec(NG, sizeof(TG));   // interleave of the geometric layout
+    static_assert(NC <= kWave, "one wave per element");
+
+    // A: t-interpolated field [c][j][i], then the staged wJ, then the
+    // s-projected field [c][j][i].  B: s-interpolated field [c][b][i], turned
+    // in place into the r-direction result [c][b][i].
+    constexpr int WBYTES = NPG * static_cast<int>(sizeof(TG)) + 8;   // staged wJ (+ misalignment slack)
+    constexpr int AV = NG * SA;
+    constexpr int A_VALUES = AV * static_cast<int>(sizeof(TC)) > WBYTES ? AV
+                                                                        : (WBYTES + sizeof(TC) - 1) / sizeof(TC);
+    __shared__ __align__(16) TC sA[A_VALUES];
+    __shared__ __align__(16) TC sB[NG * SB];
+
+    const int L = threadIdx.x;
+    const int64_t e = e0 + blockIdx.x;
+
+    // half tables, uniform across the wave
+    TC Ie[HG][HQ], Io[GE > 0 ? GE : 1][QE > 0 ? QE : 1];
+#pragma unroll
+    for (int a = 0; a < HG; ++a)
+#pragma unroll
+        for (int m = 0; m < HQ; ++m) {
+            const double v0 = I1d[a * NQ + m], v1 = I1d[a * NQ + NQ - 1 - m];
+            Ie[a][m] = static_cast<TC>(m == NQ - 1 - m ? v0 : 0.5 * (v0 + v1));
+            if (a < GE && m < QE) Io[a][m] = static_cast<TC>(0.5 * (v0 - v1));
+        }
+
+    // the u column of lane (i,j) and this lane's pieces of the element's wJ
+    const int li = L % NQ, lj = L / NQ;
+    const bool gll = L < NC;
+    TC uc[NQ];
+    {
+        const int64_t base = e * NP + (gll ? L : 0);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
+    }
+    // wJ pieces: 8-byte pieces for FP64 data, dwords otherwise (16-bit values:
+    // the dwords wholly inside the element plus a half-filled first one; a
+    // last value sharing its dword with the next element is fetched alone)
+    constexpr int PB = sizeof(TG) == 8 ? 8 : 4;                  // piece bytes
+    constexpr int VPP = PB / static_cast<int>(sizeof(TG));       // values per piece
+    constexpr int NPC = NPG / VPP + 1;
+    constexpr int PPL = (NPC + kWave - 1) / kWave;               // pieces per lane
+    using Piece = typename std::conditional<PB == 8, unsigned long long, uint32_t>::type;
+    const int64_t v0 = e * NPG;
+    const int64_t p0 = v0 / VPP, np = (v0 + NPG) / VPP - p0;
+    const int off = static_cast<int>(v0 - p0 * VPP);
+    const bool tail = VPP == 2 && ((v0 + NPG) % 2) == 1;
+    Piece wst[PPL];
+    uint16_t wlast = 0;
+    {
+        const Piece *wp = reinterpret_cast<const Piece *>(wJ) + p0;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const int t = L + q * kWave;
+            wst[q] = t < np ? __builtin_nontemporal_load(wp + t) : Piece(0);
+        }
+        if (tail && L == 0) wlast = reinterpret_cast<const uint16_t *>(wJ)[v0 + NPG - 1];
+    }
+
+    // t-interpolation: lanes (i,j)
+    if (gll) {
+        TC z[NG];
+        line_interp<NQ>(uc, z, Ie, Io);
+#pragma unroll
+        for (int c = 0; c < NG; ++c) sA[c * SA + lj * P + li] = z[c];
+    }
+    __syncthreads();
+
+    // s-interpolation: lines (i,c)
+#pragma unroll
+    for (int pass = 0; pass < (NQ * NG + kWave - 1) / kWave; ++pass) {
+        const int line = L + pass * kWave;
+        if (line < NQ * NG) {
+            const int i = line % NQ, c = line / NQ;
+            TC x[NQ], z[NG];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) x[m] = sA[c * SA + m * P + i];
+            line_interp<NQ>(x, z, Ie, Io);
+#pragma unroll
+            for (int b = 0; b < NG; ++b) sB[c * SB + b * P + i] = z[b];
+        }
+    }
+    __syncthreads();   // A is free: stage wJ there
+    {
+        Piece *sw = reinterpret_cast<Piece *>(sA);
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const int t = L + q * kWave;
+            if (t < np) sw[t] = wst[q];
+        }
+        if (tail && L == 0) reinterpret_cast<uint16_t *>(sA)[off + NPG - 1] = wlast;
+    }
+    __syncthreads();
+
+    // r-direction: lines (b,c): interpolate, scale by wJ, project, in place
+    {
+        const TG *sw = reinterpret_cast<const TG *>(sA) + off;
+#pragma unroll
+        for (int pass = 0; pass < (NG * NG + kWave - 1) / kWave; ++pass) {
+            const int line = L + pass * kWave;
+            if (line < NG * NG) {
+                const int b = line % NG, c = line / NG;
+                TC x[NQ], z[NG], w[NQ];
+                TC *row = sB + c * SB + b * P;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) x[m] = row[m];
+                line_interp<NQ>(x, z, Ie, Io);
+#pragma unroll
+                for (int a = 0; a < NG; ++a) z[a] *= to_compute(sw[geo_offset(a + NG * b, c, NG, W)], TC{});
+                line_project<NQ>(z, w, Ie, Io);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) row[m] = w[m];
+            }
+        }
+    }
+    __syncthreads();
+
+    // with beta != 0 the old y column of lane (i,j) is requested here, so its
+    // latency hides behind the s-projection
+    TC yold[NQ];
+    if (beta != TC(0) && gll) {
+        const int64_t base = e * NP + L;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) yold[k] = static_cast<TC>(y[base + k * NC]);
+    }
+
+    // s-projection: lines (i,c) -> A[c][j][i]
+#pragma unroll
+    for (int pass = 0; pass < (NQ * NG + kWave - 1) / kWave; ++pass) {
+        const int line = L + pass * kWave;
+        if (line < NQ * NG) {
+            const int i = line % NQ, c = line / NQ;
+            TC v[NG], w[NQ];
+#pragma unroll
+            for (int b = 0; b < NG; ++b) v[b] = sB[c * SB + b * P + i];
+            line_project<NQ>(v, w, Ie, Io);
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) sA[c * SA + j * P + i] = w[j];
+        }
+    }
+    __syncthreads();
+
+    // t-projection: lanes (i,j) -> y[k][j][i]
+    double dp = 0.0;
+    if (gll) {
+        TC v[NG], w[NQ];
+#pragma unroll
+        for (int c = 0; c < NG; ++c) v[c] = sA[c * SA + lj * P + li];
+        line_project<NQ>(v, w, Ie, Io);
+        const int64_t base = e * NP + L;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            TC r = w[k] * oscale;
+            const int64_t idx = base + k * NC;
+            if (beta != TC(0)) r += beta * yold[k];
+            y[idx] = static_cast<TY>(r);
+            if constexpr (DOT) dp += uc[k] * r;
+        }
+    }
+    if constexpr (DOT) {
+        static_assert(std::is_same<TV, double>::value, "element partials of FP64 fields");
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+        if (L == 0) part[e] = dp;
+    }
+}
+
+template <int NQ, class TG, class TV>
+hipError_t bp10t_launch_t(const ApplyArgs &a, hipStream_t s)
+{
+    using TC = typename compute_pair<TG, TV>::type;
+    using TY = typename output_of<TV>::type;
+    if (a.E < 1) return hipSuccess;
+    if (a.part && !std::is_same<TV, double>::value) return hipErrorInvalidValue;
+    const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
+                                                                         : a.out_scale);
+    // one workgroup per element; a grid cap splits the elements over launches
+    const int64_t chunk = a.grid_cap > 0 ? a.grid_cap : a.E;
+    for (int64_t e0 = 0; e0 < a.E; e0 += chunk) {
+        const unsigned grid = static_cast<unsigned>(a.E - e0 < chunk ? a.E - e0 : chunk);
+        if constexpr (std::is_same<TV, double>::value) {
+            if (a.part) {
+                hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV, true>), dim3(grid), dim3(kWave), 0, s, a.E, a.I1d,
+                                   static_cast<const TG *>(a.wJ), static_cast<const TV *>(a.u),
+                                   static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale, a.part, e0);
+                continue;
+            }
+        }
+        hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV>), dim3(grid), dim3(kWave), 0, s, a.E, a.I1d,
+                           static_cast<const TG *>(a.wJ), static_cast<const TV *>(a.u),
+                           static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale, nullptr, e0);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fem

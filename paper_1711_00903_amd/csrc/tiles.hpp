@@ -5,7 +5,7 @@
 // works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
 // (the GLL phases use a subset of those threads).  One exception: BP1.0 with
 // one element per workgroup and Nq <= 8 runs one wave per element with the
-// even-odd contractions of bp10w.hpp.
+// line-per-lane even-odd contractions of bp10t.hpp.
 #pragma once
 
 #include <array>
@@ -32,17 +32,16 @@ constexpr int bp30_slot_values(int nq, int bytes)
 }
 
 // BP1.0 with one element per workgroup and Nq <= 8 runs the one-wave
-// even-odd kernel (bp10w.hpp).
+// line-per-lane kernel (bp10t.hpp).
 constexpr bool bp10_wave(int nq, int epb) { return epb == 1 && nq <= 8; }
 
-constexpr int bp10w_lds_bytes(int nq, int bytes, int gbytes)
+constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 {
-    const int ng = nq + 1, hg = (ng + 1) / 2, hq = (nq + 1) / 2;
-    const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
-    const int su = nq * nq * pq, sb = nq * ng * pg;
-    const int full = bytes == 8 ? 1 : ng * nq;   // FP64 reads the full table from global memory
-    const int wst = gbytes < 8 ? (ng * ng * ng / (4 / gbytes) + 1) * 4 : 4;   // staged scaled Jacobians
-    return (4 * hg * hq + full + (su > sb ? su : sb) + nq * nq * pg) * bytes + wst;
+    const int ng = nq + 1;
+    const int p = lds_row(nq, bytes);
+    const int av = ng * nq * p;                                       // [c][j][i] volume
+    const int wv = (ng * ng * ng * gbytes + 8 + bytes - 1) / bytes;   // staged scaled Jacobians
+    return ((av > wv ? av : wv) + ng * ng * p) * bytes;
 }
 
 // LDS bytes of one workgroup for values of `bytes` bytes (tables included);
@@ -51,7 +50,7 @@ constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
 {
     const int ng = nq + 1;
     const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
-    if (op == 0 && bp10_wave(nq, epb)) return bp10w_lds_bytes(nq, bytes, gbytes);
+    if (op == 0 && bp10_wave(nq, epb)) return bp10t_lds_bytes(nq, bytes, gbytes);
     if (op == 1) return (nq * nq + 3 * epb * nq * nq * pq) * bytes;
     if (op == 0) {
         const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
@@ -87,6 +86,7 @@ constexpr std::array<int, 4> epb_choices(int op, int nq)
 // else the smallest packing that does.
 constexpr int epb_default(int op, int nq)
 {
+    if (op == 0 && nq >= 5 && nq <= 8) return 1;   // the one-wave BP1.0 kernel (measured fastest, N = 4..7)
     const int cols = columns(op, nq);
     if (cols * 5 >= round_up_wave(cols) * 4) return 1;
     const auto ch = epb_choices(op, nq);
