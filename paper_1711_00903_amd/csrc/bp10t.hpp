@@ -30,66 +30,9 @@
 #pragma once
 
 #include "bp35.hpp"
+#include "lines.hpp"
 
 namespace fem {
-
-// Interpolation of one line: x (NQ values) -> y (NG = NQ+1 values).
-template <int NQ, class TC>
-__device__ __forceinline__ void line_interp(const TC *x, TC *y, const TC (*Ie)[(NQ + 1) / 2],
-                                            const TC (*Io)[NQ / 2 > 0 ? NQ / 2 : 1])
-{
-    constexpr int NG = NQ + 1, QE = NQ / 2, GE = NG / 2, HG = (NG + 1) / 2;
-    TC xp[QE > 0 ? QE : 1], xm[QE > 0 ? QE : 1];
-#pragma unroll
-    for (int m = 0; m < QE; ++m) {
-        xp[m] = x[m] + x[NQ - 1 - m];
-        xm[m] = x[m] - x[NQ - 1 - m];
-    }
-#pragma unroll
-    for (int a = 0; a < HG; ++a) {
-        TC ev = 0, od = 0;
-#pragma unroll
-        for (int m = 0; m < QE; ++m) ev += Ie[a][m] * xp[m];
-        if constexpr (NQ % 2 == 1) ev += Ie[a][QE] * x[QE];
-        if (a < GE) {
-#pragma unroll
-            for (int m = 0; m < QE; ++m) od += Io[a][m] * xm[m];
-            y[a] = ev + od;
-            y[NG - 1 - a] = ev - od;
-        } else {
-            y[a] = ev;   // middle Gauss point (NG odd)
-        }
-    }
-}
-
-// Projection of one line: v (NG values) -> w (NQ values), w_i = sum_a I[a][i] v_a.
-template <int NQ, class TC>
-__device__ __forceinline__ void line_project(const TC *v, TC *w, const TC (*Ie)[(NQ + 1) / 2],
-                                             const TC (*Io)[NQ / 2 > 0 ? NQ / 2 : 1])
-{
-    constexpr int NG = NQ + 1, QE = NQ / 2, GE = NG / 2, HQ = (NQ + 1) / 2;
-    TC vp[GE > 0 ? GE : 1], vm[GE > 0 ? GE : 1];
-#pragma unroll
-    for (int a = 0; a < GE; ++a) {
-        vp[a] = v[a] + v[NG - 1 - a];
-        vm[a] = v[a] - v[NG - 1 - a];
-    }
-#pragma unroll
-    for (int i = 0; i < HQ; ++i) {
-        TC ev = 0, od = 0;
-#pragma unroll
-        for (int a = 0; a < GE; ++a) ev += Ie[a][i] * vp[a];
-        if constexpr (NG % 2 == 1) ev += Ie[GE][i] * v[GE];
-        if (i < QE) {
-#pragma unroll
-            for (int a = 0; a < GE; ++a) od += Io[a][i] * vm[a];
-            w[i] = ev + od;
-            w[NQ - 1 - i] = ev - od;
-        } else {
-            w[i] = ev;   // middle GLL point (NQ odd)
-        }
-    }
-}
 
 // DOT: also write part[e] = sum over the element's nodes of u * y (y the final
 // output), reduced across the wave in a fixed order.
@@ -127,14 +70,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
 
     // half tables, uniform across the wave
     TC Ie[HG][HQ], Io[GE > 0 ? GE : 1][QE > 0 ? QE : 1];
-#pragma unroll
-    for (int a = 0; a < HG; ++a)
-#pragma unroll
-        for (int m = 0; m < HQ; ++m) {
-            const double v0 = I1d[a * NQ + m], v1 = I1d[a * NQ + NQ - 1 - m];
-            Ie[a][m] = static_cast<TC>(m == NQ - 1 - m ? v0 : 0.5 * (v0 + v1));
-            if (a < GE && m < QE) Io[a][m] = static_cast<TC>(0.5 * (v0 - v1));
-        }
+    interp_half_tables<NQ>(I1d, Ie, Io);
 
     // the u column of lane (i,j) and this lane's pieces of the element's wJ
     const int li = L % NQ, lj = L / NQ;

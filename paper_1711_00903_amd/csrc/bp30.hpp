@@ -14,14 +14,16 @@
 #pragma once
 
 #include "bp35.hpp"
+#include "bp30t.hpp"
 
 namespace fem {
 
-// Minimum waves per SIMD asked of the register allocator.  At Nq = 8 (and
-// Nq = 6 with one element per workgroup) the kernel then fits 256 VGPRs without
-// spills and runs two waves per SIMD instead of one (4.0 instead of 5.7 ms at
-// N = 7, E = 262144); elsewhere the cap would spill, so it is not set.
-constexpr int bp30_min_waves(int nq, int epb) { return (nq == 8 || (nq == 6 && epb == 1)) ? 2 : 1; }
+// Minimum waves per SIMD asked of the register allocator.  At Nq = 8 the
+// multi-element packings then fit 256 VGPRs without spills and run two waves
+// per SIMD instead of one (4.0 instead of 5.7 ms at N = 7, E = 262144);
+// elsewhere the cap would spill, so it is not set.  (One element per
+// workgroup at Nq <= 8 runs bp30t_kernel instead.)
+constexpr int bp30_min_waves(int nq, int epb) { return (nq == 8 && epb > 1) ? 2 : 1; }
 
 template <int NQ, int EPB, class TG, class TV>
 __global__ __launch_bounds__(threads_for(2, NQ, EPB))
@@ -257,7 +259,10 @@ hipError_t bp30_launch_nq(const ApplyArgs &a, hipStream_t s)
 {
     constexpr auto ch = epb_choices(2, NQ);
     const int epb = a.epb > 0 ? a.epb : epb_default(2, NQ);
-    if (epb == ch[0]) return bp30_launch_t<NQ, ch[0], TG, TV>(a, s);
+    if (epb == ch[0]) {
+        if constexpr (bp30_line(NQ, ch[0])) return bp30t_launch_t<NQ, TG, TV>(a, s);
+        else return bp30_launch_t<NQ, ch[0], TG, TV>(a, s);
+    }
     if constexpr (ch[1] > 0) if (epb == ch[1]) return bp30_launch_t<NQ, ch[1], TG, TV>(a, s);
     if constexpr (ch[2] > 0) if (epb == ch[2]) return bp30_launch_t<NQ, ch[2], TG, TV>(a, s);
     if constexpr (ch[3] > 0) if (epb == ch[3]) return bp30_launch_t<NQ, ch[3], TG, TV>(a, s);

@@ -1,0 +1,250 @@
+// bp30t.hpp -- BP3.0 de-aliased stiffness for Nq <= 8, one element per
+// workgroup of ceil(Ng^2 / 64) waves, one-direction contractions done by the
+// lane that owns a whole line (Alg. 5 with the interpolation and projection
+// of Alg. 1-2).
+//
+// Lane (a,b) of the Gauss grid owns column (a,b) for the metric step and
+// requests all 6 Ng geometric factors of that column before the first
+// barrier, so the element's whole geometric read (81% of its bytes) is in
+// flight while the field is interpolated.  Every other step is a line product
+// with a uniform half table (lines.hpp), and the element turns between line
+// directions through LDS:
+//   t-interpolation  lanes (i,j): u column (registers)      -> A[c][j][i]
+//   s-interpolation  lines (i,c): A[c][*][i]                -> B[c][b][i]
+//   r-interpolation  lines (b,c): B[c][b][*]                -> U[c][b][a]   (u~ at Gauss points)
+//   r-, s-derivative lines (b,c) and (a,c) of U             -> QR, QS
+//   metric           columns (a,b): t-derivative of the U column, then
+//                    (wr,ws,wt) = G (qr,qs,qt); WR, WS over QR, QS; the column's
+//                    D~^T wt (+ lambda wJ u~) over its U column          -> V
+//   s-transpose      lines (a,c): WS[c][*][a] <- D~^T WS[c][*][a]
+//   r-transpose      lines (b,c): D~^T WR[c][b][*] + V + WS, then projected -> X[c][b][i]
+//   s-projection     lines (i,c): X[c][*][i]                -> Y[c][j][i]
+//   t-projection     lanes (i,j): Y[*][j][i]                -> y[k][j][i]
+// Three LDS volumes (Ng^3 each, rows padded) are reused:
+//   V0: A, then QR / WR, then Y;  V1: B, then QS / WS;  V2: U, then V, then X.
+// The interpolation and derivative half tables are live in different phases
+// (only both in the r-transpose), which keeps the registers for the factors.
+#pragma once
+
+#include "bp35.hpp"
+#include "lines.hpp"
+
+namespace fem {
+
+constexpr int bp30t_threads(int nq) { return round_up_wave((nq + 1) * (nq + 1)); }
+
+template <int NQ, class TG, class TV>
+__global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
+    int64_t E, const double *__restrict__ I1d, const double *__restrict__ Dgl, const TG *__restrict__ G,
+    const TG *__restrict__ wJ, typename compute_pair<TG, TV>::type lambda, const TV *__restrict__ u,
+    typename output_of<TV>::type *__restrict__ y, typename compute_pair<TG, TV>::type beta,
+    typename compute_pair<TG, TV>::type oscale, int64_t e0)
+{
+    using TC = typename compute_pair<TG, TV>::type;
+    using TY = typename output_of<TV>::type;
+    constexpr int NG = NQ + 1;
+    constexpr int NC = NQ * NQ;
+    constexpr int NP = NC * NQ;
+    constexpr int NCG = NG * NG;
+    constexpr int NPG = NCG * NG;
+    constexpr int HG = (NG + 1) / 2, HQ = (NQ + 1) / 2, GE = NG / 2, QE = NQ / 2;
+    constexpr int P = lds_row(NG, sizeof(TC));   // row length of every volume
+    constexpr int S = NG * P;                    // slab
+    constexpr int VOL = NG * S;
+    constexpr int W = geo_vec(NG, sizeof(TG));
+    static_assert(NCG <= bp30t_threads(NQ), "one lane per Gauss column");
+
+    __shared__ __align__(16) TC V0[VOL];
+    __shared__ __align__(16) TC V1[VOL];
+    __shared__ __align__(16) TC V2[VOL];
+
+    const int L = threadIdx.x;
+    const int64_t e = e0 + blockIdx.x;
+    const bool col = L < NCG;                    // owns Gauss column (ca, cb)
+    const int ca = L % NG, cb = L / NG;
+
+    // the u column of lane (i,j) and the 6 Ng factors of Gauss column (ca,cb)
+    const bool gll = L < NC;
+    const int li = L % NQ, lj = L / NQ;
+    TC uc[NQ];
+    {
+        const int64_t base = e * NP + (gll ? L : 0);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
+    }
+    TC g[6][NG];
+    {
+        const int64_t gb = e * (6 * NPG);
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+            for (int c = 0; c < NG; ++c)
+                g[f][c] = col ? ld_stream<TC>(G, gb + f * NPG + geo_offset(ca + NG * cb, c, NG, W)) : TC(0);
+    }
+
+    {
+        TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
+        interp_half_tables<NQ>(I1d, Ie, Io);
+        // t-interpolation: lanes (i,j) -> V0 = A[c][j][i]
+        if (gll) {
+            TC z[NG];
+            line_interp<NQ>(uc, z, Ie, Io);
+#pragma unroll
+            for (int c = 0; c < NG; ++c) V0[c * S + lj * P + li] = z[c];
+        }
+        __syncthreads();
+        // s-interpolation: lines (i,c) -> V1 = B[c][b][i]
+        if (L < NQ * NG) {
+            const int i = L % NQ, c = L / NQ;
+            TC x[NQ], z[NG];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) x[m] = V0[c * S + m * P + i];
+            line_interp<NQ>(x, z, Ie, Io);
+#pragma unroll
+            for (int b = 0; b < NG; ++b) V1[c * S + b * P + i] = z[b];
+        }
+        __syncthreads();
+        // r-interpolation: lines (b,c) -> V2 = U[c][b][a]
+        if (L < NCG) {
+            const int b = L % NG, c = L / NG;
+            TC x[NQ], z[NG];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) x[m] = V1[c * S + b * P + m];
+            line_interp<NQ>(x, z, Ie, Io);
+#pragma unroll
+            for (int a = 0; a < NG; ++a) V2[c * S + b * P + a] = z[a];
+        }
+        __syncthreads();
+    }
+
+    TC Dp[GE][HG], Dm[HG][GE];
+    deriv_half_tables<NG>(Dgl, Dp, Dm);
+    // r- and s-derivatives of U: lines (b,c) -> V0 = QR, lines (a,c) -> V1 = QS
+    if (L < NCG) {
+        const int p = L % NG, c = L / NG;
+        TC x[NG], z[NG];
+#pragma unroll
+        for (int m = 0; m < NG; ++m) x[m] = V2[c * S + p * P + m];   // row (b = p)
+        line_deriv<NG>(x, z, Dp, Dm);
+#pragma unroll
+        for (int a = 0; a < NG; ++a) V0[c * S + p * P + a] = z[a];
+#pragma unroll
+        for (int m = 0; m < NG; ++m) x[m] = V2[c * S + m * P + p];   // column (a = p)
+        line_deriv<NG>(x, z, Dp, Dm);
+#pragma unroll
+        for (int b = 0; b < NG; ++b) V1[c * S + b * P + p] = z[b];
+    }
+    __syncthreads();
+
+    // metric step on Gauss column (ca,cb)
+    if (col) {
+        const int o = cb * P + ca;
+        TC ut[NG], qt[NG], wt[NG], vt[NG];
+#pragma unroll
+        for (int c = 0; c < NG; ++c) ut[c] = V2[c * S + o];
+        line_deriv<NG>(ut, qt, Dp, Dm);
+#pragma unroll
+        for (int c = 0; c < NG; ++c) {
+            const TC qr = V0[c * S + o], qs = V1[c * S + o];
+            const TC grr = g[0][c], grs = g[1][c], grt = g[2][c], gss = g[3][c], gst = g[4][c], gtt = g[5][c];
+            V0[c * S + o] = grr * qr + grs * qs + grt * qt[c];
+            V1[c * S + o] = grs * qr + gss * qs + gst * qt[c];
+            wt[c] = grt * qr + gst * qs + gtt * qt[c];
+        }
+        line_deriv_t<NG>(wt, vt, Dp, Dm);
+        if (lambda != TC(0)) {
+            const int64_t wb = e * NPG;
+#pragma unroll
+            for (int c = 0; c < NG; ++c)
+                vt[c] += lambda * ld<TC>(wJ, wb + geo_offset(ca + NG * cb, c, NG, W)) * ut[c];
+        }
+#pragma unroll
+        for (int c = 0; c < NG; ++c) V2[c * S + o] = vt[c];
+    }
+    __syncthreads();
+
+    // s-transpose: lines (a,c) of WS, in place
+    if (L < NCG) {
+        const int a = L % NG, c = L / NG;
+        TC v[NG], w[NG];
+#pragma unroll
+        for (int b = 0; b < NG; ++b) v[b] = V1[c * S + b * P + a];
+        line_deriv_t<NG>(v, w, Dp, Dm);
+#pragma unroll
+        for (int b = 0; b < NG; ++b) V1[c * S + b * P + a] = w[b];
+    }
+    // the old y column of lane (i,j) when beta != 0, requested early
+    TC yold[NQ];
+    if (beta != TC(0) && gll) {
+        const int64_t base = e * NP + L;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) yold[k] = static_cast<TC>(y[base + k * NC]);
+    }
+    __syncthreads();
+
+    {
+        TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
+        interp_half_tables<NQ>(I1d, Ie, Io);
+        // r-transpose and the sum of the three terms, then r-projection: lines (b,c) -> V2 = X[c][b][i]
+        if (L < NCG) {
+            const int b = L % NG, c = L / NG;
+            TC v[NG], w[NG], x[NQ];
+#pragma unroll
+            for (int a = 0; a < NG; ++a) v[a] = V0[c * S + b * P + a];
+            line_deriv_t<NG>(v, w, Dp, Dm);
+#pragma unroll
+            for (int a = 0; a < NG; ++a) w[a] += V2[c * S + b * P + a] + V1[c * S + b * P + a];
+            line_project<NQ>(w, x, Ie, Io);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) V2[c * S + b * P + i] = x[i];
+        }
+        __syncthreads();
+        // s-projection: lines (i,c) -> V0 = Y[c][j][i]
+        if (L < NQ * NG) {
+            const int i = L % NQ, c = L / NQ;
+            TC v[NG], w[NQ];
+#pragma unroll
+            for (int b = 0; b < NG; ++b) v[b] = V2[c * S + b * P + i];
+            line_project<NQ>(v, w, Ie, Io);
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) V0[c * S + j * P + i] = w[j];
+        }
+        __syncthreads();
+        // t-projection: lanes (i,j) -> y[k][j][i]
+        if (gll) {
+            TC v[NG], w[NQ];
+#pragma unroll
+            for (int c = 0; c < NG; ++c) v[c] = V0[c * S + lj * P + li];
+            line_project<NQ>(v, w, Ie, Io);
+            const int64_t base = e * NP + L;
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                TC r = w[k] * oscale;
+                if (beta != TC(0)) r += beta * yold[k];
+                y[base + k * NC] = static_cast<TY>(r);
+            }
+        }
+    }
+}
+
+template <int NQ, class TG, class TV>
+hipError_t bp30t_launch_t(const ApplyArgs &a, hipStream_t s)
+{
+    using TC = typename compute_pair<TG, TV>::type;
+    using TY = typename output_of<TV>::type;
+    if (a.E < 1) return hipSuccess;
+    const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
+                                                                         : a.out_scale);
+    // one workgroup per element; a grid cap splits the elements over launches
+    const int64_t chunk = a.grid_cap > 0 ? a.grid_cap : a.E;
+    for (int64_t e0 = 0; e0 < a.E; e0 += chunk) {
+        const unsigned grid = static_cast<unsigned>(a.E - e0 < chunk ? a.E - e0 : chunk);
+        hipLaunchKernelGGL((bp30t_kernel<NQ, TG, TV>), dim3(grid), dim3(bp30t_threads(NQ)), 0, s, a.E, a.I1d,
+                           a.Dgl, static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
+                           static_cast<TC>(a.lambda), static_cast<const TV *>(a.u), static_cast<TY *>(a.y),
+                           static_cast<TC>(a.beta), oscale, e0);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fem

@@ -3,9 +3,10 @@
 // Every kernel maps one thread to one (i,j) column of an element (a vertical
 // line of nodes along t) and packs `epb` elements into one workgroup.  BP3.5
 // works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
-// (the GLL phases use a subset of those threads).  One exception: BP1.0 with
-// one element per workgroup and Nq <= 8 runs one wave per element with the
-// line-per-lane even-odd contractions of bp10t.hpp.
+// (the GLL phases use a subset of those threads).  Exceptions: with one element
+// per workgroup and Nq <= 8, BP1.0 runs one wave per element with the
+// line-per-lane even-odd contractions of bp10t.hpp, and BP3.0 the
+// line-per-lane kernel of bp30t.hpp (one lane per Gauss column).
 #pragma once
 
 #include <array>
@@ -44,6 +45,16 @@ constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
     return ((av > wv ? av : wv) + ng * ng * p) * bytes;
 }
 
+// BP3.0 with one element per workgroup and Nq <= 8 runs the line-per-lane
+// kernel (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes.
+constexpr bool bp30_line(int nq, int epb) { return epb == 1 && nq <= 8; }
+
+constexpr int bp30t_lds_bytes(int nq, int bytes)
+{
+    const int ng = nq + 1;
+    return 3 * ng * ng * lds_row(ng, bytes) * bytes;
+}
+
 // LDS bytes of one workgroup for values of `bytes` bytes (tables included);
 // gbytes: stored size of a geometric value (BP1.0 one-wave staging).
 constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
@@ -51,6 +62,7 @@ constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
     const int ng = nq + 1;
     const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
     if (op == 0 && bp10_wave(nq, epb)) return bp10t_lds_bytes(nq, bytes, gbytes);
+    if (op == 2 && bp30_line(nq, epb)) return bp30t_lds_bytes(nq, bytes);
     if (op == 1) return (nq * nq + 3 * epb * nq * nq * pq) * bytes;
     if (op == 0) {
         const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
@@ -87,6 +99,7 @@ constexpr std::array<int, 4> epb_choices(int op, int nq)
 constexpr int epb_default(int op, int nq)
 {
     if (op == 0 && nq >= 5 && nq <= 8) return 1;   // the one-wave BP1.0 kernel (measured fastest, N = 4..7)
+    if (op == 2 && nq >= 4 && nq <= 8) return 1;   // the line-per-lane BP3.0 kernel (FP64, N = 3..7)
     const int cols = columns(op, nq);
     if (cols * 5 >= round_up_wave(cols) * 4) return 1;
     const auto ch = epb_choices(op, nq);
