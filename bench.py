@@ -8,6 +8,10 @@ the HBM roofline fraction of the kernel (algorithmic bytes / average kernel
 time, timed with events on the stream the kernel runs on, against 8 TB/s), the
 measured device-to-device copy roofline, and the FP64 CPU oracle timed on the
 host's cores on a bounded sample of the same workload.
+
+``--workload`` selects another single-operator workload with the same record
+(BP1.0 or BP3.0, N = 7, on the 64^3 mesh); ``--cg``, ``--sweep`` and
+``--batch`` run the solver, the roofline sweep and the ragged batch.
 """
 from __future__ import annotations
 
@@ -26,16 +30,23 @@ HBM_PEAK_GBS = 8000.0
 N = 7
 GRID = 32
 
+# single-operator workloads: (operator, N, grid edge); E = edge^3
+BENCH_WORKLOADS = {
+    "bp35_n7_e32768": ("BP35", 7, 32),
+    "bp10_n7_e262144": ("BP10", 7, 64),
+    "bp30_n7_e262144": ("BP30", 7, 64),
+}
+# the sources whose hash must match the committed HBM counters of a workload
+KERNEL_SOURCES = {
+    "BP35": ["bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
+    "BP10": ["bp10.hpp", "bp10t.hpp", "lines.hpp", "bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
+    "BP30": ["bp30.hpp", "bp30t.hpp", "lines.hpp", "bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
+}
+OP_LABEL = {"BP10": "BP1.0", "BP35": "BP3.5", "BP30": "BP3.0"}
+
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
-
-
-def alg_bytes_bp35(N: int, E: int, sbytes: int = 8, ybytes: int = 8, nfactors: int = 6) -> int:
-    """Algorithmic HBM bytes of one BP3.5 apply: u read once, each factor read
-    once, y written once (lambda = 0, beta = 0)."""
-    npn = (N + 1) ** 3
-    return E * npn * (sbytes + ybytes + nfactors * sbytes)
 
 
 def copy_roofline(fem, torch, nbytes: int, reps: int = 20) -> dict:
@@ -70,9 +81,10 @@ def copy_roofline(fem, torch, nbytes: int, reps: int = 20) -> dict:
     return out
 
 
-def measured_traffic(kernel_sources: list[str], record: str) -> float | None:
+def measured_traffic(kernel_sources: list[str], record: str, epb: int) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, if the kernel's sources are unchanged since the counters were taken."""
+    summary, if the kernel's sources are unchanged since the counters were taken
+    and the launch uses the same packing."""
     import hashlib
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
@@ -82,35 +94,36 @@ def measured_traffic(kernel_sources: list[str], record: str) -> float | None:
     for s in kernel_sources:
         with open(os.path.join(ROOT, "paper_1711_00903_amd", "csrc", s), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if h.hexdigest() != rec.get("source_sha256") or rec.get("epb") != epb:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(X, u, budget_s: float) -> dict:
+def cpu_baseline(op: str, Nb: int, X, u, budget_s: float) -> dict:
     """The FP64 oracle (plain C, OpenMP over elements) on the host's cores,
     repeated over the first elements of the workload for about budget_s."""
     import oracle
     threads = oracle.set_threads(0)
-    pb = oracle.Problem(N, X)
-    G = pb.G_gll()
     E = X.shape[0]
+    pb = oracle.Problem(Nb, X[:min(E, 16384)])
+    apply = {"BP10": pb.mass, "BP35": pb.stiff35, "BP30": pb.stiff30}[op]
+    apply(u[:min(E, 8)])   # geometry built outside the timing
     # size the sample so that one pass takes ~1/5 of the budget
     Es = min(E, 512)
     t0 = time.perf_counter()
-    oracle.bp35(N, G[:Es], u[:Es])
+    apply(u[:Es])
     dt = time.perf_counter() - t0
-    Es = int(min(E, max(512, Es * (budget_s / 5) / max(dt, 1e-6))))
+    Es = int(min(pb.E, max(512, Es * (budget_s / 5) / max(dt, 1e-6))))
     times = []
     t_end = time.perf_counter() + budget_s
     while True:
         t0 = time.perf_counter()
-        oracle.bp35(N, G[:Es], u[:Es])
+        apply(u[:Es])
         times.append(time.perf_counter() - t0)
         if time.perf_counter() > t_end:
             break
     t = float(np.median(times))
-    return {"value": Es * (N + 1) ** 3 / t / 1e9, "unit": "GDOF/s", "cores": threads,
+    return {"value": Es * (Nb + 1) ** 3 / t / 1e9, "unit": "GDOF/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {Es} of {E} elements of the same mesh and field, "
                       f"{len(times)} passes, median pass {t * 1e3:.1f} ms"}
@@ -298,6 +311,7 @@ def run_batch(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="bp35_n7_e32768", choices=sorted(BENCH_WORKLOADS))
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
@@ -355,22 +369,36 @@ def main() -> int:
         return 1
     fem.lib()
     torch.cuda.set_device(0)
+    workload = args.workload
+    op, Nb, grid = BENCH_WORKLOADS[workload]
+    opid = fem.OP_NAMES[op]
     if args.epb or args.grid_cap:
-        fem.fem_tune_set(fem.FEM_OP_BP35, N, fem.FEM_F64, args.epb, args.grid_cap)
+        fem.fem_tune_set(opid, Nb, fem.FEM_F64, args.epb, args.grid_cap)
 
-    log(f"bench: BP3.5 N={N} E={GRID ** 3}: building inputs")
-    X = workloads.element_vertices(GRID)
+    log(f"bench: {OP_LABEL[op]} N={Nb} E={grid ** 3}: building inputs")
+    X = workloads.element_vertices(grid)
     E = X.shape[0]
-    u = workloads.field(E, N + 1)
-    dev = DeviceMesh(N, X, h=1.0 / GRID)
+    u = workloads.field(E, Nb + 1)
+    dev = DeviceMesh(Nb, X, h=1.0 / grid)
     ut = torch.from_numpy(u).cuda()
     y = torch.empty_like(ut)
-    G, _ = dev.geometry(fem.FEM_QUAD_GLL, want_wJ=False)
     stream = torch.cuda.current_stream()
+    if op == "BP35":
+        G, _ = dev.geometry(fem.FEM_QUAD_GLL, want_wJ=False)
 
-    def step():
-        fem.fem_stiff_collocated_apply(N, E, dev.D1d, G, None, 0.0, ut, y, 0.0, fem.FEM_F64, 1.0,
-                                       stream)
+        def step():
+            fem.fem_stiff_collocated_apply(Nb, E, dev.D1d, G, None, 0.0, ut, y, 0.0, fem.FEM_F64, 1.0, stream)
+    elif op == "BP10":
+        _, wJ = dev.geometry(fem.FEM_QUAD_GL, want_G=False, kind="wJ")
+
+        def step():
+            fem.fem_mass_apply(Nb, E, dev.I1d, wJ, ut, y, 0.0, fem.FEM_F64, 1.0, stream)
+    else:
+        G, _ = dev.geometry(fem.FEM_QUAD_GL, want_wJ=False)
+
+        def step():
+            fem.fem_stiff_dealiased_apply(Nb, E, dev.I1d, dev.Dgl, G, None, 0.0, ut, y, 0.0, fem.FEM_F64,
+                                          1.0, stream)
 
     for _ in range(args.warmup):
         step()
@@ -391,9 +419,10 @@ def main() -> int:
     ms_per_step = wall * 1e3 / args.steps
     log(f"bench: {args.steps} steps, {ms_per_step:.4f} ms/step wall, kernel {kern_ms:.4f} ms")
 
-    epb = fem.fem_tune_get(fem.FEM_OP_BP35, N, fem.FEM_F64)[0]
-    dofs = E * (N + 1) ** 3
-    bytes_launch = alg_bytes_bp35(N, E)
+    from paper_1711_00903_amd import tune
+    epb = fem.fem_tune_get(opid, Nb, fem.FEM_F64)[0] or fem.fem_supported_epb(opid, Nb, fem.FEM_F64)[0]
+    dofs = E * (Nb + 1) ** 3
+    bytes_launch = tune.alg_bytes(op, Nb, E, fem.FEM_F64)
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
     copy = copy_roofline(fem, torch, bytes_launch)
     log(f"bench: copy roofline {copy}")
@@ -401,10 +430,15 @@ def main() -> int:
     cpu = None
     if args.cpu_budget > 0:
         log("bench: timing the CPU oracle")
-        cpu = cpu_baseline(X, u, args.cpu_budget)
+        cpu = cpu_baseline(op, Nb, X, u, args.cpu_budget)
 
+    kname = {"BP35": f"bp35_kernel<{Nb + 1},{epb},double,double>",
+             "BP10": f"bp10t_kernel<{Nb + 1},double,double>" if epb == 1 and Nb <= 7
+             else f"bp10_kernel<{Nb + 1},{epb},double,double>",
+             "BP30": f"bp30t_kernel<{Nb + 1},double,double>" if epb == 1 and Nb <= 7
+             else f"bp30_kernel<{Nb + 1},{epb},double,double>"}[op]
     rec = {
-        "metric": "BP3.5 N=7 GDOF/s (FP64, 32^3 perturbed hex mesh)",
+        "metric": f"{OP_LABEL[op]} N={Nb} GDOF/s (FP64, {grid}^3 perturbed hex mesh)",
         "value": dofs / (ms_per_step * 1e-3) / 1e9,
         "unit": "GDOF/s",
         "n_gpus": 1,
@@ -416,15 +450,14 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "bp35_n7_e32768", "op": "BP3.5", "N": N, "E": E,
-                   "dofs": dofs, "factors": 6, "lambda": 0.0, "storage": "f64",
+        "config": {"workload": workload, "op": OP_LABEL[op], "N": Nb, "E": E,
+                   "dofs": dofs, "factors": 0 if op == "BP10" else 6, "lambda": 0.0, "storage": "f64",
                    "epb": epb,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(["bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
-                                                 "bp35_n7_e32768_f64_traffic.json") if epb == 1 else None,
-                     "kernel": f"bp35_kernel<{N + 1},{epb},double>", "kernel_ms": kern_ms,
+                     "traffic": measured_traffic(KERNEL_SOURCES[op], f"{workload}_f64_traffic.json", epb),
+                     "kernel": kname, "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": bytes_launch},
         "copy_roofline": {"GB/s": copy["best"], "kernel_GB/s": copy["kernel"],
                           "memcpy_GB/s": copy["memcpy"], "bytes": bytes_launch,
