@@ -75,8 +75,22 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
     // the u column of lane (i,j) and this lane's pieces of the element's wJ
     const int li = L % NQ, lj = L / NQ;
     const bool gll = L < NC;
+    // 16-bit fields: the element's u block is fetched in 16-byte pieces by all
+    // lanes and turned into columns through LDS (B is free until the
+    // s-interpolation), instead of Nq 2-byte loads per lane
+    constexpr bool USTAGE = sizeof(TV) == 2 && (NP % 8) == 0;
+    constexpr int UPL = (NP / 8 + kWave - 1) / kWave;   // pieces per lane
+    using R16 = typename raw_vec<16>::type;
     TC uc[NQ];
-    {
+    R16 upc[USTAGE ? UPL : 1];
+    if constexpr (USTAGE) {
+        const R16 *src = reinterpret_cast<const R16 *>(u + e * NP);
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int t = L + q * kWave;
+            upc[q] = t < NP / 8 ? src[t] : R16{};
+        }
+    } else {
         const int64_t base = e * NP + (gll ? L : 0);
 #pragma unroll
         for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
@@ -103,6 +117,28 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
             wst[q] = t < np ? __builtin_nontemporal_load(wp + t) : Piece(0);
         }
         if (tail && L == 0) wlast = reinterpret_cast<const uint16_t *>(wJ)[v0 + NPG - 1];
+    }
+
+    if constexpr (USTAGE) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int t = L + q * kWave;
+            if (t < NP / 8) {
+                TV tmp[8];
+                __builtin_memcpy(tmp, &upc[q], 16);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int n = t * 8 + v;
+                    const int k = n / NC, r = n - k * NC;
+                    sB[k * NQ * P + (r / NQ) * P + r % NQ] = to_compute(tmp[v], TC{});
+                }
+            }
+        }
+        __syncthreads();
+        if (gll) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) uc[k] = sB[k * NQ * P + lj * P + li];
+        }
     }
 
     // t-interpolation: lanes (i,j)

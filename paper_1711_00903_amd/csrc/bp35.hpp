@@ -116,6 +116,13 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     // narrower geometric data the packed factors leave VGPRs free and the LDS
     // copy is faster than the SGPR spills the scalar entries cause.
     constexpr bool SCALAR_TAB = std::is_same<TC, double>::value && std::is_same<TG, double>::value;
+    // 16-bit fields: the group's u block (contiguous) is fetched in 16-byte
+    // pieces by all threads and staged in LDS, instead of Nq 2-byte loads per
+    // lane (address-bound); each lane then reads its column back from LDS.
+    constexpr int NT = threads_for(1, NQ, EPB);
+    constexpr bool USTAGE = !XP && sizeof(TV) == 2 && (NP % 8) == 0;
+    constexpr int UPIECES = EPB * NP / 8;
+    constexpr int UPPT = (UPIECES + NT - 1) / NT;
 
     __shared__ TC s_D[NQ * NQ];
     __shared__ TC s_u[EPB * VOL];
@@ -164,9 +171,23 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
                 uc[k] = rv[k] + bp * uc[k];
                 if (ok) pw[base + k * NC] = uc[k];
             }
-        } else {
+        } else if constexpr (!USTAGE) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
+        }
+        using R16 = typename raw_vec<16>::type;
+        R16 upc[USTAGE ? UPPT : 1];
+        int npieces = 0;
+        if constexpr (USTAGE) {
+            const int64_t g0 = g * EPB;
+            const int nvalid = static_cast<int>((E - g0) < EPB ? (E - g0) : EPB);
+            npieces = nvalid * (NP / 8);
+            const R16 *src = reinterpret_cast<const R16 *>(u + g0 * NP);
+#pragma unroll
+            for (int q = 0; q < UPPT; ++q) {
+                const int t = static_cast<int>(threadIdx.x) + q * NT;
+                upc[q] = t < npieces ? src[t] : R16{};
+            }
         }
         const TG *Ge = G + (ok ? e : 0) * (6 * NP) + col * W;
         constexpr int NV = NQ / W;   // vectors per factor and column
@@ -184,11 +205,32 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             }
         }
         TC gw[PREF ? 1 : 6 * W];    // non-prefetched: the factors of W slabs at a time
-        if (lane) {
+        if constexpr (USTAGE) {
+#pragma unroll
+            for (int q = 0; q < UPPT; ++q) {
+                const int t = static_cast<int>(threadIdx.x) + q * NT;
+                if (t < npieces) {
+                    TV tmp[8];
+                    __builtin_memcpy(tmp, &upc[q], 16);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int n0 = t * 8 + v;
+                        const int gs = n0 / NP, n = n0 - gs * NP;
+                        const int k = n / NC, r = n - k * NC;
+                        const int jj = r / NQ, ii = r - jj * NQ;
+                        s_u[gs * VOL + k * SLAB + jj * P + ii] = to_compute(tmp[v], TC{});
+                    }
+                }
+            }
+        } else if (lane) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) su[k * SLAB + me] = uc[k];
         }
         __syncthreads();
+        if constexpr (USTAGE) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) uc[k] = su[k * SLAB + me];
+        }
 
         TC wt[NQ];
 #pragma unroll

@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 MESHES = [("BP35", 7, 27), ("BP10", 3, 64), ("BP30", 5, 20), ("BP35", 2, 100), ("BP30", 1, 7),
-          ("BP10", 11, 8), ("BP35", 14, 5), ("BP30", 9, 12)]
+          ("BP10", 11, 8), ("BP35", 14, 5), ("BP30", 9, 12), ("BP10", 6, 30), ("BP30", 7, 9)]
 
 
 @pytest.fixture(scope="module")
