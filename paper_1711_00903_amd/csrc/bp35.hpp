@@ -204,7 +204,22 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
                 for (int x = 0; x < 6 * NV; ++x) gp[x].zero();
             }
         }
-        TC gw[PREF ? 1 : 6 * W];    // non-prefetched: the factors of W slabs at a time
+        // beyond Nq = 10 the factors of each group of W slabs are requested
+        // GDIST groups ahead of their use (occupancy is one wave per SIMD
+        // there, so the wave's own requests must cover the HBM latency).
+        // Measured at E = 262144: +4..23% for Nq = 11..14; at Nq >= 15 the
+        // extra registers cost more than the latency they hide, so the factors
+        // are requested at use.
+        constexpr int GDIST = NQ >= 15 ? 0 : 2;
+        packed_vec<W, TG> gq[PREF ? 1 : NV][6];
+        if constexpr (!PREF) {
+            if (ok) {
+#pragma unroll
+                for (int q = 0; q < (GDIST < NV ? GDIST : NV); ++q)
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) gq[q][f].stream(Ge + f * NP + q * NC * W);
+            }
+        }
         if constexpr (USTAGE) {
 #pragma unroll
             for (int q = 0; q < UPPT; ++q) {
@@ -253,16 +268,16 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
                 gst = gp[4 * NV + k / W].template get<TC>(k % W);
                 gtt = gp[5 * NV + k / W].template get<TC>(k % W);
             } else if (ok) {
-                if (k % W == 0) {
+                if (k % W == 0 && k / W + GDIST < NV) {
 #pragma unroll
-                    for (int f = 0; f < 6; ++f) ld_stream_vec<W>(Ge + f * NP + (k / W) * NC * W, gw + f * W);
+                    for (int f = 0; f < 6; ++f) gq[k / W + GDIST][f].stream(Ge + f * NP + (k / W + GDIST) * NC * W);
                 }
-                grr = gw[0 * W + k % W];
-                grs = gw[1 * W + k % W];
-                grt = gw[2 * W + k % W];
-                gss = gw[3 * W + k % W];
-                gst = gw[4 * W + k % W];
-                gtt = gw[5 * W + k % W];
+                grr = gq[k / W][0].template get<TC>(k % W);
+                grs = gq[k / W][1].template get<TC>(k % W);
+                grt = gq[k / W][2].template get<TC>(k % W);
+                gss = gq[k / W][3].template get<TC>(k % W);
+                gst = gq[k / W][4].template get<TC>(k % W);
+                gtt = gq[k / W][5].template get<TC>(k % W);
             }
             const TC wr = grr * qr + grs * qs + grt * qt;
             const TC ws = grs * qr + gss * qs + gst * qt;
