@@ -1,5 +1,6 @@
-// bp10t.hpp -- BP1.0 mass operator, one wave64 per element (Nq <= 8), with
-// every one-direction contraction done by a lane that owns a whole line.
+// bp10t.hpp -- BP1.0 mass operator, one element per workgroup of
+// ceil(Nq^2 / 64) waves (Nq <= 10), with every one-direction contraction done
+// by a lane that owns a whole line.
 //
 // The six contractions of Alg. 1-3 (interpolate t, s, r; scale by wJ; project
 // r, s, t) are each a small matrix times one line of the element.  Here a lane
@@ -17,8 +18,8 @@
 // and projection (I^T) of a Gauss line v uses the same half tables with the
 // roles of the indices exchanged.
 //
-// Phases (N = 7: Nq = 8, Ng = 9; lines over one wave, the second pass of a
-// phase with more than 64 lines uses the first lanes again):
+// Phases (N = 7: Nq = 8, Ng = 9, one wave; a phase with more lines than the
+// workgroup has lanes takes a second pass over the first lanes):
 //   t-interpolation  lanes (i,j): u column in registers -> A[c][j][i]          64 lines
 //   s-interpolation  lines (i,c): A[c][*][i]            -> B[c][b][i]          72 lines
 //   r-direction      lines (b,c): B[c][b][*] -> interpolate, x wJ, project -> B[c][b][*] (in place)   81 lines
@@ -36,8 +37,10 @@ namespace fem {
 
 // DOT: also write part[e] = sum over the element's nodes of u * y (y the final
 // output), reduced across the wave in a fixed order.
+constexpr int bp10t_threads(int nq) { return round_up_wave(nq * nq); }
+
 template <int NQ, class TG, class TV, bool DOT = false>
-__global__ __launch_bounds__(kWave) void bp10t_kernel(
+__global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     int64_t E, const double *__restrict__ I1d, const TG *__restrict__ wJ, const TV *__restrict__ u,
     typename output_of<TV>::type *__restrict__ y, typename compute_pair<TG, TV>::type beta,
     typename compute_pair<TG, TV>::type oscale, double *__restrict__ part = nullptr, int64_t e0 = 0)
@@ -53,7 +56,8 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
     constexpr int SA = NQ * P;                   // slab of A: [j][i]
     constexpr int SB = NG * P;                   // slab of B: [b][i]
     constexpr int W = geo_vec(NG, sizeof(TG));   // interleave of the geometric layout
-    static_assert(NC <= kWave, "one wave per element");
+    constexpr int NT = bp10t_threads(NQ);
+    static_assert(NC <= NT, "one lane per GLL column");
 
     // A: t-interpolated field [c][j][i], then the staged wJ, then the
     // s-projected field [c][j][i].  B: s-interpolated field [c][b][i], turned
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
     // lanes and turned into columns through LDS (B is free until the
     // s-interpolation), instead of Nq 2-byte loads per lane
     constexpr bool USTAGE = sizeof(TV) == 2 && (NP % 8) == 0;
-    constexpr int UPL = (NP / 8 + kWave - 1) / kWave;   // pieces per lane
+    constexpr int UPL = (NP / 8 + NT - 1) / NT;   // pieces per lane
     using R16 = typename raw_vec<16>::type;
     TC uc[NQ];
     R16 upc[USTAGE ? UPL : 1];
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
         const R16 *src = reinterpret_cast<const R16 *>(u + e * NP);
 #pragma unroll
         for (int q = 0; q < UPL; ++q) {
-            const int t = L + q * kWave;
+            const int t = L + q * NT;
             upc[q] = t < NP / 8 ? src[t] : R16{};
         }
     } else {
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
     constexpr int PB = sizeof(TG) == 8 ? 8 : 4;                  // piece bytes
     constexpr int VPP = PB / static_cast<int>(sizeof(TG));       // values per piece
     constexpr int NPC = NPG / VPP + 1;
-    constexpr int PPL = (NPC + kWave - 1) / kWave;               // pieces per lane
+    constexpr int PPL = (NPC + NT - 1) / NT;               // pieces per lane
     using Piece = typename std::conditional<PB == 8, unsigned long long, uint32_t>::type;
     const int64_t v0 = e * NPG;
     const int64_t p0 = v0 / VPP, np = (v0 + NPG) / VPP - p0;
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
         const Piece *wp = reinterpret_cast<const Piece *>(wJ) + p0;
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const int t = L + q * kWave;
+            const int t = L + q * NT;
             wst[q] = t < np ? __builtin_nontemporal_load(wp + t) : Piece(0);
         }
         if (tail && L == 0) wlast = reinterpret_cast<const uint16_t *>(wJ)[v0 + NPG - 1];
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
     if constexpr (USTAGE) {
 #pragma unroll
         for (int q = 0; q < UPL; ++q) {
-            const int t = L + q * kWave;
+            const int t = L + q * NT;
             if (t < NP / 8) {
                 TV tmp[8];
                 __builtin_memcpy(tmp, &upc[q], 16);
@@ -152,8 +156,8 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
 
     // s-interpolation: lines (i,c)
 #pragma unroll
-    for (int pass = 0; pass < (NQ * NG + kWave - 1) / kWave; ++pass) {
-        const int line = L + pass * kWave;
+    for (int pass = 0; pass < (NQ * NG + NT - 1) / NT; ++pass) {
+        const int line = L + pass * NT;
         if (line < NQ * NG) {
             const int i = line % NQ, c = line / NQ;
             TC x[NQ], z[NG];
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
         Piece *sw = reinterpret_cast<Piece *>(sA);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const int t = L + q * kWave;
+            const int t = L + q * NT;
             if (t < np) sw[t] = wst[q];
         }
         if (tail && L == 0) reinterpret_cast<uint16_t *>(sA)[off + NPG - 1] = wlast;
@@ -180,8 +184,8 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
     {
         const TG *sw = reinterpret_cast<const TG *>(sA) + off;
 #pragma unroll
-        for (int pass = 0; pass < (NG * NG + kWave - 1) / kWave; ++pass) {
-            const int line = L + pass * kWave;
+        for (int pass = 0; pass < (NG * NG + NT - 1) / NT; ++pass) {
+            const int line = L + pass * NT;
             if (line < NG * NG) {
                 const int b = line % NG, c = line / NG;
                 TC x[NQ], z[NG], w[NQ];
@@ -210,8 +214,8 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
 
     // s-projection: lines (i,c) -> A[c][j][i]
 #pragma unroll
-    for (int pass = 0; pass < (NQ * NG + kWave - 1) / kWave; ++pass) {
-        const int line = L + pass * kWave;
+    for (int pass = 0; pass < (NQ * NG + NT - 1) / NT; ++pass) {
+        const int line = L + pass * NT;
         if (line < NQ * NG) {
             const int i = line % NQ, c = line / NQ;
             TC v[NG], w[NQ];
@@ -245,7 +249,20 @@ __global__ __launch_bounds__(kWave) void bp10t_kernel(
         static_assert(std::is_same<TV, double>::value, "element partials of FP64 fields");
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
-        if (L == 0) part[e] = dp;
+        if constexpr (NT == kWave) {
+            if (L == 0) part[e] = dp;
+        } else {
+            // one partial per wave, summed in wave order
+            __shared__ double s_red[NT / kWave];
+            if (L % kWave == 0) s_red[L / kWave] = dp;
+            __syncthreads();
+            if (L == 0) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / kWave; ++w) t += s_red[w];
+                part[e] = t;
+            }
+        }
     }
 }
 
@@ -264,13 +281,13 @@ hipError_t bp10t_launch_t(const ApplyArgs &a, hipStream_t s)
         const unsigned grid = static_cast<unsigned>(a.E - e0 < chunk ? a.E - e0 : chunk);
         if constexpr (std::is_same<TV, double>::value) {
             if (a.part) {
-                hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV, true>), dim3(grid), dim3(kWave), 0, s, a.E, a.I1d,
+                hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV, true>), dim3(grid), dim3(bp10t_threads(NQ)), 0, s, a.E, a.I1d,
                                    static_cast<const TG *>(a.wJ), static_cast<const TV *>(a.u),
                                    static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale, a.part, e0);
                 continue;
             }
         }
-        hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV>), dim3(grid), dim3(kWave), 0, s, a.E, a.I1d,
+        hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV>), dim3(grid), dim3(bp10t_threads(NQ)), 0, s, a.E, a.I1d,
                            static_cast<const TG *>(a.wJ), static_cast<const TV *>(a.u),
                            static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale, nullptr, e0);
     }

@@ -4,9 +4,9 @@
 // line of nodes along t) and packs `epb` elements into one workgroup.  BP3.5
 // works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
 // (the GLL phases use a subset of those threads).  Exceptions: with one element
-// per workgroup and Nq <= 8, BP1.0 runs one wave per element with the
-// line-per-lane even-odd contractions of bp10t.hpp, and BP3.0 the
-// line-per-lane kernel of bp30t.hpp (one lane per Gauss column).
+// per workgroup, BP1.0 (Nq <= 10) runs the line-per-lane even-odd
+// contractions of bp10t.hpp with one lane per GLL column, and BP3.0 (Nq <= 8)
+// the line-per-lane kernel of bp30t.hpp with one lane per Gauss column.
 #pragma once
 
 #include <array>
@@ -32,9 +32,9 @@ constexpr int bp30_slot_values(int nq, int bytes)
     return r1 + r2 + ng * ng * pg;
 }
 
-// BP1.0 with one element per workgroup and Nq <= 8 runs the one-wave
-// line-per-lane kernel (bp10t.hpp).
-constexpr bool bp10_wave(int nq, int epb) { return epb == 1 && nq <= 8; }
+// BP1.0 with one element per workgroup and Nq <= 10 runs the line-per-lane
+// kernel (bp10t.hpp): ceil(Nq^2 / 64) waves, one for Nq <= 8.
+constexpr bool bp10_wave(int nq, int epb) { return epb == 1 && nq <= 10; }
 
 constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 {
@@ -73,7 +73,7 @@ constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
 
 constexpr int threads_for(int op, int nq, int epb)
 {
-    return op == 0 && bp10_wave(nq, epb) ? kWave : round_up_wave(columns(op, nq) * epb);
+    return op == 0 && bp10_wave(nq, epb) ? round_up_wave(nq * nq) : round_up_wave(columns(op, nq) * epb);
 }
 
 // Up to four supported elements-per-workgroup values: 1, then those that fill
@@ -98,7 +98,7 @@ constexpr std::array<int, 4> epb_choices(int op, int nq)
 // else the smallest packing that does.
 constexpr int epb_default(int op, int nq)
 {
-    if (op == 0 && nq >= 5 && nq <= 8) return 1;   // the one-wave BP1.0 kernel (measured fastest, N = 4..7)
+    if (op == 0 && nq >= 5 && nq <= 10) return 1;  // the line-per-lane BP1.0 kernel (measured fastest, N = 4..9)
     if (op == 2 && nq >= 4 && nq <= 8) return 1;   // the line-per-lane BP3.0 kernel (FP64, N = 3..7)
     const int cols = columns(op, nq);
     if (cols * 5 >= round_up_wave(cols) * 4) return 1;
