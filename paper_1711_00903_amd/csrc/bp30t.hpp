@@ -1,12 +1,12 @@
-// bp30t.hpp -- BP3.0 de-aliased stiffness for Nq <= 8, one element per
+// bp30t.hpp -- BP3.0 de-aliased stiffness for Nq <= 10, one element per
 // workgroup of ceil(Ng^2 / 64) waves, one-direction contractions done by the
 // lane that owns a whole line (Alg. 5 with the interpolation and projection
 // of Alg. 1-2).
 //
 // Lane (a,b) of the Gauss grid owns column (a,b) for the metric step and
-// requests all 6 Ng geometric factors of that column before the first
-// barrier, so the element's whole geometric read (81% of its bytes) is in
-// flight while the field is interpolated.  Every other step is a line product
+// (up to Ng = 9) requests all 6 Ng geometric factors of that column before the
+// first barrier, so the element's whole geometric read (81% of its bytes) is
+// in flight while the field is interpolated.  Every other step is a line product
 // with a uniform half table (lines.hpp), and the element turns between line
 // directions through LDS:
 //   t-interpolation  lanes (i,j): u column (registers)      -> A[c][j][i]
@@ -72,15 +72,19 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
 #pragma unroll
         for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
     }
+    // up to Ng = 9 every slab of the column's factors is requested here; beyond,
+    // the first GPRE slabs, and each later slab GPRE slabs ahead of its use in
+    // the metric step (all of them no longer fit in registers)
+    constexpr int GPRE = NG <= 9 ? NG : 4;
     TC g[6][NG];
-    {
-        const int64_t gb = e * (6 * NPG);
+    const int64_t gb = e * (6 * NPG);
+    auto gload = [&](int c) {
 #pragma unroll
         for (int f = 0; f < 6; ++f)
+            g[f][c] = col ? ld_stream<TC>(G, gb + f * NPG + geo_offset(ca + NG * cb, c, NG, W)) : TC(0);
+    };
 #pragma unroll
-            for (int c = 0; c < NG; ++c)
-                g[f][c] = col ? ld_stream<TC>(G, gb + f * NPG + geo_offset(ca + NG * cb, c, NG, W)) : TC(0);
-    }
+    for (int c = 0; c < GPRE; ++c) gload(c);
 
     {
         TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
@@ -145,6 +149,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
         line_deriv<NG>(ut, qt, Dp, Dm);
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
+            if (c + GPRE < NG) gload(c + GPRE);
             const TC qr = V0[c * S + o], qs = V1[c * S + o];
             const TC grr = g[0][c], grs = g[1][c], grt = g[2][c], gss = g[3][c], gst = g[4][c], gtt = g[5][c];
             V0[c * S + o] = grr * qr + grs * qs + grt * qt[c];

@@ -5,7 +5,7 @@
 // works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
 // (the GLL phases use a subset of those threads).  Exceptions: with one element
 // per workgroup, BP1.0 (Nq <= 10) runs the line-per-lane even-odd
-// contractions of bp10t.hpp with one lane per GLL column, and BP3.0 (Nq <= 8)
+// contractions of bp10t.hpp with one lane per GLL column, and BP3.0 (Nq <= 10)
 // the line-per-lane kernel of bp30t.hpp with one lane per Gauss column.
 #pragma once
 
@@ -45,9 +45,9 @@ constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
     return ((av > wv ? av : wv) + ng * ng * p) * bytes;
 }
 
-// BP3.0 with one element per workgroup and Nq <= 8 runs the line-per-lane
+// BP3.0 with one element per workgroup and Nq <= 10 runs the line-per-lane
 // kernel (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes.
-constexpr bool bp30_line(int nq, int epb) { return epb == 1 && nq <= 8; }
+constexpr bool bp30_line(int nq, int epb) { return epb == 1 && nq <= 10; }
 
 constexpr int bp30t_lds_bytes(int nq, int bytes)
 {
@@ -99,7 +99,7 @@ constexpr std::array<int, 4> epb_choices(int op, int nq)
 constexpr int epb_default(int op, int nq)
 {
     if (op == 0 && nq >= 5 && nq <= 10) return 1;  // the line-per-lane BP1.0 kernel (measured fastest, N = 4..9)
-    if (op == 2 && nq >= 4 && nq <= 8) return 1;   // the line-per-lane BP3.0 kernel (FP64, N = 3..7)
+    if (op == 2 && nq >= 4 && nq <= 10) return 1;  // the line-per-lane BP3.0 kernel (FP64, N = 3..9)
     const int cols = columns(op, nq);
     if (cols * 5 >= round_up_wave(cols) * 4) return 1;
     const auto ch = epb_choices(op, nq);
