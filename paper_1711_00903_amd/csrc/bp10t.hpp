@@ -1,5 +1,5 @@
 // bp10t.hpp -- BP1.0 mass operator, one element per workgroup of
-// ceil(Nq^2 / 64) waves (Nq <= 10), with every one-direction contraction done
+// ceil(Nq^2 / 64) waves (Nq <= 12), with every one-direction contraction done
 // by a lane that owns a whole line.
 //
 // The six contractions of Alg. 1-3 (interpolate t, s, r; scale by wJ; project

@@ -1,4 +1,4 @@
-// bp30t.hpp -- BP3.0 de-aliased stiffness for Nq <= 10, one element per
+// bp30t.hpp -- BP3.0 de-aliased stiffness for Nq <= 12, one element per
 // workgroup of ceil(Ng^2 / 64) waves, one-direction contractions done by the
 // lane that owns a whole line (Alg. 5 with the interpolation and projection
 // of Alg. 1-2).
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     // up to Ng = 9 every slab of the column's factors is requested here; beyond,
     // the first GPRE slabs, and each later slab GPRE slabs ahead of its use in
     // the metric step (all of them no longer fit in registers)
-    constexpr int GPRE = NG <= 9 ? NG : 4;
+    constexpr int GPRE = NG <= 9 ? NG : (NG <= 11 ? 4 : 3);
     TC g[6][NG];
     const int64_t gb = e * (6 * NPG);
     auto gload = [&](int c) {

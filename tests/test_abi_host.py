@@ -74,10 +74,10 @@ def test_tune_table(fem):
                 assert th % 64 == 0 and 64 <= th <= 512
                 assert 0 < lds <= 160 * 1024
     # BP1.0 with one element per workgroup runs the line-per-lane kernel up to
-    # N = 9 (one lane per GLL column: one wave up to N = 7)
+    # N = 11 (one lane per GLL column: one wave up to N = 7)
     for N in range(1, 16):
         th, _ = fem.fem_kernel_info(fem.FEM_OP_BP10, N, fem.FEM_F64, 1)
-        if N <= 9:
+        if N <= 11:
             assert th == (N + 1) ** 2 + (-(N + 1) ** 2) % 64, (N, th)
         else:
             assert th == (N + 2) ** 2 + (-(N + 2) ** 2) % 64, (N, th)
