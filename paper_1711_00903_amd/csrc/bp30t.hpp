@@ -64,37 +64,49 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     const int ca = L % NG, cb = L / NG;
 
     // the u column of lane (i,j) and the 6 Ng factors of Gauss column (ca,cb)
+    // Every lane loads (lanes beyond the columns re-read column 0 and never use
+    // it): a load under a lane condition makes the compiler widen a narrow
+    // value inside the branch and wait for it there, one load at a time.
     const bool gll = L < NC;
     const int li = L % NQ, lj = L / NQ;
     TC uc[NQ];
     {
         const int64_t base = e * NP + (gll ? L : 0);
+        TV raw[NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
+        for (int k = 0; k < NQ; ++k) raw[k] = u[base + k * NC];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) uc[k] = to_compute(raw[k], TC{});
     }
     // up to Ng = 9 every slab of the column's factors is requested here; beyond,
     // the first GPRE slabs, and each later slab GPRE slabs ahead of its use in
-    // the metric step (all of them no longer fit in registers)
+    // the metric step (all of them no longer fit in registers).  The factors
+    // stay in their stored type until the metric step: a widening right after
+    // the load would wait for every request before the first barrier.
     constexpr int GPRE = NG <= 9 ? NG : (NG <= 11 ? 4 : 3);
-    TC g[6][NG];
+    TG g[6][NG];
     const int64_t gb = e * (6 * NPG);
+    const int gcol = col ? L : 0;
     auto gload = [&](int c) {
 #pragma unroll
-        for (int f = 0; f < 6; ++f)
-            g[f][c] = col ? ld_stream<TC>(G, gb + f * NPG + geo_offset(ca + NG * cb, c, NG, W)) : TC(0);
+        for (int f = 0; f < 6; ++f) g[f][c] = nt_load(G + gb + f * NPG + geo_offset(gcol, c, NG, W));
     };
 #pragma unroll
     for (int c = 0; c < GPRE; ++c) gload(c);
+    __builtin_amdgcn_sched_barrier(0);   // the requests go out before the u column is waited for
 
     {
         TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
         interp_half_tables<NQ>(I1d, Ie, Io);
-        // t-interpolation: lanes (i,j) -> V0 = A[c][j][i]
-        if (gll) {
+        // t-interpolation: lanes (i,j) -> V0 = A[c][j][i].  Every lane computes
+        // and stores (lanes beyond the columns into row Nq, which no later phase
+        // reads), so that the u loads stay ahead of the factor loads.
+        {
             TC z[NG];
             line_interp<NQ>(uc, z, Ie, Io);
+            const int row = gll ? lj : NQ;
 #pragma unroll
-            for (int c = 0; c < NG; ++c) V0[c * S + lj * P + li] = z[c];
+            for (int c = 0; c < NG; ++c) V0[c * S + row * P + li] = z[c];
         }
         __syncthreads();
         // s-interpolation: lines (i,c) -> V1 = B[c][b][i]
@@ -151,7 +163,9 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
         for (int c = 0; c < NG; ++c) {
             if (c + GPRE < NG) gload(c + GPRE);
             const TC qr = V0[c * S + o], qs = V1[c * S + o];
-            const TC grr = g[0][c], grs = g[1][c], grt = g[2][c], gss = g[3][c], gst = g[4][c], gtt = g[5][c];
+            const TC grr = to_compute(g[0][c], TC{}), grs = to_compute(g[1][c], TC{}),
+                     grt = to_compute(g[2][c], TC{}), gss = to_compute(g[3][c], TC{}),
+                     gst = to_compute(g[4][c], TC{}), gtt = to_compute(g[5][c], TC{});
             V0[c * S + o] = grr * qr + grs * qs + grt * qt[c];
             V1[c * S + o] = grs * qr + gss * qs + gst * qt[c];
             wt[c] = grt * qr + gst * qs + gtt * qt[c];

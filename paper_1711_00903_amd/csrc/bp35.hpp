@@ -67,12 +67,17 @@ __device__ __forceinline__ void stage_fields(TC *__restrict__ s_w, const TV *__r
     constexpr int NP = NQ * NQ * NQ;
     constexpr int NS = (EPB * NP + NT - 1) / NT;
     const int total = nvalid * NP;
-    TC v[NS];
+    // unconditional loads (a clamped index past the group): a narrow value loaded
+    // under a condition is widened inside the branch, one wait per load
+    TV raw[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int x = static_cast<int>(threadIdx.x) + s * NT;
-        v[s] = x < total ? ld<TC>(ug, x) : TC(0);
+        raw[s] = ug[x < total ? x : 0];
     }
+    TC v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = to_compute(raw[s], TC{});
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int x = static_cast<int>(threadIdx.x) + s * NT;
