@@ -111,6 +111,9 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     const int64_t p0 = v0 / VPP, np = (v0 + NPG) / VPP - p0;
     const int off = static_cast<int>(v0 - p0 * VPP);
     const bool tail = VPP == 2 && ((v0 + NPG) % 2) == 1;
+    // The loads are unconditional (clamped indices; the surplus is never
+    // stored): with a load under a lane condition the compiler no longer counts
+    // the requests in flight and waits for all of them before the t-interpolation.
     Piece wst[PPL];
     uint16_t wlast = 0;
     {
@@ -118,9 +121,9 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
             const int t = L + q * NT;
-            wst[q] = t < np ? __builtin_nontemporal_load(wp + t) : Piece(0);
+            wst[q] = __builtin_nontemporal_load(wp + (t < np ? t : np - 1));
         }
-        if (tail && L == 0) wlast = reinterpret_cast<const uint16_t *>(wJ)[v0 + NPG - 1];
+        if constexpr (VPP == 2) wlast = reinterpret_cast<const uint16_t *>(wJ)[v0 + NPG - 1];
     }
 
     if constexpr (USTAGE) {

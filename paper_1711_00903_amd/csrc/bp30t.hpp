@@ -63,21 +63,20 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     const bool col = L < NCG;                    // owns Gauss column (ca, cb)
     const int ca = L % NG, cb = L / NG;
 
-    // the u column of lane (i,j) and the 6 Ng factors of Gauss column (ca,cb)
+    // the u column of lane (i,j) and the 6 Ng factors of Gauss column (ca,cb).
     // Every lane loads (lanes beyond the columns re-read column 0 and never use
-    // it): a load under a lane condition makes the compiler widen a narrow
-    // value inside the branch and wait for it there, one load at a time.
+    // it): under a lane condition the compiler widens a narrow value inside the
+    // branch and waits for it there, one load at a time.  The u column is
+    // requested first and waited for only after the factor requests are out.
     const bool gll = L < NC;
     const int li = L % NQ, lj = L / NQ;
-    TC uc[NQ];
+    TV uraw[NQ];
     {
         const int64_t base = e * NP + (gll ? L : 0);
-        TV raw[NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) raw[k] = u[base + k * NC];
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) uc[k] = to_compute(raw[k], TC{});
+        for (int k = 0; k < NQ; ++k) uraw[k] = u[base + k * NC];
     }
+    __builtin_amdgcn_sched_barrier(0);
     // up to Ng = 9 every slab of the column's factors is requested here; beyond,
     // the first GPRE slabs, and each later slab GPRE slabs ahead of its use in
     // the metric step (all of them no longer fit in registers).  The factors
@@ -93,20 +92,23 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     };
 #pragma unroll
     for (int c = 0; c < GPRE; ++c) gload(c);
-    __builtin_amdgcn_sched_barrier(0);   // the requests go out before the u column is waited for
+    __builtin_amdgcn_sched_barrier(0);
+    TC uc[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        uc[k] = to_compute(uraw[k], TC{});
+        asm volatile("" : "+v"(uc[k]));   // keeps the u loads out of the branch below
+    }
 
     {
         TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
         interp_half_tables<NQ>(I1d, Ie, Io);
-        // t-interpolation: lanes (i,j) -> V0 = A[c][j][i].  Every lane computes
-        // and stores (lanes beyond the columns into row Nq, which no later phase
-        // reads), so that the u loads stay ahead of the factor loads.
-        {
+        // t-interpolation: lanes (i,j) -> V0 = A[c][j][i]
+        if (gll) {
             TC z[NG];
             line_interp<NQ>(uc, z, Ie, Io);
-            const int row = gll ? lj : NQ;
 #pragma unroll
-            for (int c = 0; c < NG; ++c) V0[c * S + row * P + li] = z[c];
+            for (int c = 0; c < NG; ++c) V0[c * S + lj * P + li] = z[c];
         }
         __syncthreads();
         // s-interpolation: lines (i,c) -> V1 = B[c][b][i]

@@ -161,6 +161,10 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         const bool ok = lane && e < E;
         const int64_t base = (ok ? e : 0) * NP + col;
 
+        // Loads are issued by every lane (lanes without an element read element
+        // 0 and never store): under a lane condition the compiler stops
+        // counting the requests in flight and waits for the factors as well
+        // before the field reaches LDS.
         TC uc[NQ];
         if constexpr (XP) {
             static_assert(std::is_same<TV, double>::value, "direction update on FP64 fields");
@@ -168,8 +172,8 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             double rv[NQ];
 #pragma unroll
             for (int k = 0; k < NQ; ++k) {
-                uc[k] = ok ? pw[base + k * NC] : 0.0;
-                rv[k] = ok ? xr[base + k * NC] : 0.0;
+                uc[k] = pw[base + k * NC];
+                rv[k] = xr[base + k * NC];
             }
 #pragma unroll
             for (int k = 0; k < NQ; ++k) {
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             }
         } else if constexpr (!USTAGE) {
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) uc[k] = ok ? ld<TC>(u, base + k * NC) : TC(0);
+            for (int k = 0; k < NQ; ++k) uc[k] = ld<TC>(u, base + k * NC);
         }
         using R16 = typename raw_vec<16>::type;
         R16 upc[USTAGE ? UPPT : 1];
@@ -199,15 +203,10 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         // gp[f * NV + k / W], lane k % W: factor f at slab k, stored precision
         packed_vec<W, TG> gp[PREF ? 6 * NV : 1];
         if constexpr (PREF) {
-            if (ok) {
 #pragma unroll
-                for (int f = 0; f < 6; ++f)
+            for (int f = 0; f < 6; ++f)
 #pragma unroll
-                    for (int kq = 0; kq < NV; ++kq) gp[f * NV + kq].stream(Ge + f * NP + kq * NC * W);
-            } else {
-#pragma unroll
-                for (int x = 0; x < 6 * NV; ++x) gp[x].zero();
-            }
+                for (int kq = 0; kq < NV; ++kq) gp[f * NV + kq].stream(Ge + f * NP + kq * NC * W);
         }
         // beyond Nq = 10 the factors of each group of W slabs are requested
         // GDIST groups ahead of their use (occupancy is one wave per SIMD
@@ -218,12 +217,10 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         constexpr int GDIST = NQ >= 15 ? 0 : 2;
         packed_vec<W, TG> gq[PREF ? 1 : NV][6];
         if constexpr (!PREF) {
-            if (ok) {
 #pragma unroll
-                for (int q = 0; q < (GDIST < NV ? GDIST : NV); ++q)
+            for (int q = 0; q < (GDIST < NV ? GDIST : NV); ++q)
 #pragma unroll
-                    for (int f = 0; f < 6; ++f) gq[q][f].stream(Ge + f * NP + q * NC * W);
-            }
+                for (int f = 0; f < 6; ++f) gq[q][f].stream(Ge + f * NP + q * NC * W);
         }
         if constexpr (USTAGE) {
 #pragma unroll
