@@ -1,6 +1,6 @@
 // bp10t.hpp -- BP1.0 mass operator, one element per workgroup of
-// ceil(Nq^2 / 64) waves (Nq <= 12), with every one-direction contraction done
-// by a lane that owns a whole line.
+// ceil(Nq^2 / 64) waves, with every one-direction contraction done by a lane
+// that owns a whole line.
 //
 // The six contractions of Alg. 1-3 (interpolate t, s, r; scale by wJ; project
 // r, s, t) are each a small matrix times one line of the element.  Here a lane
@@ -72,9 +72,25 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     const int L = threadIdx.x;
     const int64_t e = e0 + blockIdx.x;
 
-    // half tables, uniform across the wave
-    TC Ie[HG][HQ], Io[GE > 0 ? GE : 1][QE > 0 ? QE : 1];
-    interp_half_tables<NQ>(I1d, Ie, Io);
+    // half tables, uniform across the wave: in registers for small Nq, in LDS
+    // beyond (the lines then need the registers); the LDS copy is fetched
+    // before the element's loads and stored after they are issued.  Crossover
+    // measured at E = 262144: Nq = 12 is faster with LDS tables in FP32
+    // arithmetic only.
+    constexpr bool TLDS = NQ > 12 || (NQ == 12 && sizeof(TC) == 4);
+    constexpr int IOR = GE > 0 ? GE : 1, IOC = QE > 0 ? QE : 1;
+    __shared__ TC sIe[TLDS ? HG : 1][HQ];
+    __shared__ TC sIo[TLDS ? IOR : 1][IOC];
+    TC rIe[TLDS ? 1 : HG][HQ], rIo[TLDS ? 1 : IOR][IOC];
+    double tv0 = 0.0, tv1 = 0.0;
+    if constexpr (TLDS) {
+        interp_pair_load<NQ>(I1d, L, tv0, tv1);
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        interp_half_tables<NQ>(I1d, rIe, rIo);
+    }
+    const TC(*Ie)[HQ] = TLDS ? sIe : rIe;
+    const TC(*Io)[IOC] = TLDS ? sIo : rIo;
 
     // the u column of lane (i,j) and this lane's pieces of the element's wJ
     const int li = L % NQ, lj = L / NQ;
@@ -146,6 +162,11 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
 #pragma unroll
             for (int k = 0; k < NQ; ++k) uc[k] = sB[k * NQ * P + lj * P + li];
         }
+    }
+
+    if constexpr (TLDS) {
+        interp_pair_store<NQ>(sIe, sIo, L, tv0, tv1);
+        __syncthreads();
     }
 
     // t-interpolation: lanes (i,j)

@@ -22,7 +22,7 @@ namespace fem {
 // multi-element packings then fit 256 VGPRs without spills and run two waves
 // per SIMD instead of one (4.0 instead of 5.7 ms at N = 7, E = 262144);
 // elsewhere the cap would spill, so it is not set.  (One element per
-// workgroup at Nq <= 12 runs bp30t_kernel instead.)
+// workgroup runs bp30t_kernel instead.)
 constexpr int bp30_min_waves(int nq, int epb) { return (nq == 8 && epb > 1) ? 2 : 1; }
 
 template <int NQ, int EPB, class TG, class TV>

@@ -1,5 +1,5 @@
-// bp30t.hpp -- BP3.0 de-aliased stiffness for Nq <= 12, one element per
-// workgroup of ceil(Ng^2 / 64) waves, one-direction contractions done by the
+// bp30t.hpp -- BP3.0 de-aliased stiffness, one element per workgroup of
+// ceil(Ng^2 / 64) waves, one-direction contractions done by the
 // lane that owns a whole line (Alg. 5 with the interpolation and projection
 // of Alg. 1-2).
 //
@@ -70,6 +70,23 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     // requested first and waited for only after the factor requests are out.
     const bool gll = L < NC;
     const int li = L % NQ, lj = L / NQ;
+    // Half tables: in registers for small Nq, in LDS beyond (the lines then
+    // need the registers); the LDS copies are fetched ahead of the element's
+    // loads and stored once those are issued.  The crossover was measured at
+    // E = 262144: LDS from Nq = 11 (Nq = 12 in FP64 arithmetic stays faster
+    // with registers).
+    constexpr bool TLDS = NQ > 12 || NQ == 11 || (NQ == 12 && sizeof(TC) == 4);
+    constexpr int QEC = QE > 0 ? QE : 1;
+    __shared__ TC sIe[TLDS ? HG : 1][HQ];
+    __shared__ TC sIo[TLDS ? GE : 1][QEC];
+    __shared__ TC sDp[TLDS ? GE : 1][HG];
+    __shared__ TC sDm[TLDS ? HG : 1][GE];
+    double ti0 = 0.0, ti1 = 0.0, td0 = 0.0, td1 = 0.0;
+    if constexpr (TLDS) {
+        interp_pair_load<NQ>(I1d, L, ti0, ti1);
+        deriv_pair_load<NG>(Dgl, L, td0, td1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     TV uraw[NQ];
     {
         const int64_t base = e * NP + (gll ? L : 0);
@@ -82,7 +99,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     // the metric step (all of them no longer fit in registers).  The factors
     // stay in their stored type until the metric step: a widening right after
     // the load would wait for every request before the first barrier.
-    constexpr int GPRE = NG <= 9 ? NG : (NG <= 11 ? 4 : 3);
+    constexpr int GPRE = NG <= 9 ? NG : (NG <= 11 ? 4 : (NG <= 16 ? 3 : 2));
     TG g[6][NG];
     const int64_t gb = e * (6 * NPG);
     const int gcol = col ? L : 0;
@@ -93,6 +110,11 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
 #pragma unroll
     for (int c = 0; c < GPRE; ++c) gload(c);
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (TLDS) {
+        interp_pair_store<NQ>(sIe, sIo, L, ti0, ti1);
+        deriv_pair_store<NG>(sDp, sDm, L, td0, td1);
+        __syncthreads();
+    }
     TC uc[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
@@ -101,8 +123,10 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     }
 
     {
-        TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
-        interp_half_tables<NQ>(I1d, Ie, Io);
+        TC rIe[TLDS ? 1 : HG][HQ], rIo[TLDS ? 1 : GE][QEC];
+        if constexpr (!TLDS) interp_half_tables<NQ>(I1d, rIe, rIo);
+        const TC(*Ie)[HQ] = TLDS ? sIe : rIe;
+        const TC(*Io)[QEC] = TLDS ? sIo : rIo;
         // t-interpolation: lanes (i,j) -> V0 = A[c][j][i]
         if (gll) {
             TC z[NG];
@@ -135,8 +159,10 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
         __syncthreads();
     }
 
-    TC Dp[GE][HG], Dm[HG][GE];
-    deriv_half_tables<NG>(Dgl, Dp, Dm);
+    TC rDp[TLDS ? 1 : GE][HG], rDm[TLDS ? 1 : HG][GE];
+    if constexpr (!TLDS) deriv_half_tables<NG>(Dgl, rDp, rDm);
+    const TC(*Dp)[HG] = TLDS ? sDp : rDp;
+    const TC(*Dm)[GE] = TLDS ? sDm : rDm;
     // r- and s-derivatives of U: lines (b,c) -> V0 = QR, lines (a,c) -> V1 = QS
     if (L < NCG) {
         const int p = L % NG, c = L / NG;
@@ -174,10 +200,15 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
         }
         line_deriv_t<NG>(wt, vt, Dp, Dm);
         if (lambda != TC(0)) {
+            // u~ is read again from this lane's own column of V2 instead of
+            // being kept live through the metric step (measured: fewer registers
+            // and faster for Nq <= 10 and with LDS tables; slower at Nq = 11, 12)
+            constexpr bool REREAD = TLDS || NQ <= 10;
             const int64_t wb = e * NPG;
 #pragma unroll
             for (int c = 0; c < NG; ++c)
-                vt[c] += lambda * ld<TC>(wJ, wb + geo_offset(ca + NG * cb, c, NG, W)) * ut[c];
+                vt[c] += lambda * ld<TC>(wJ, wb + geo_offset(ca + NG * cb, c, NG, W)) *
+                         (REREAD ? V2[c * S + o] : ut[c]);
         }
 #pragma unroll
         for (int c = 0; c < NG; ++c) V2[c * S + o] = vt[c];
@@ -204,8 +235,10 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     __syncthreads();
 
     {
-        TC Ie[HG][HQ], Io[GE][QE > 0 ? QE : 1];
-        interp_half_tables<NQ>(I1d, Ie, Io);
+        TC rIe[TLDS ? 1 : HG][HQ], rIo[TLDS ? 1 : GE][QEC];
+        if constexpr (!TLDS) interp_half_tables<NQ>(I1d, rIe, rIo);
+        const TC(*Ie)[HQ] = TLDS ? sIe : rIe;
+        const TC(*Io)[QEC] = TLDS ? sIo : rIo;
         // r-transpose and the sum of the three terms, then r-projection: lines (b,c) -> V2 = X[c][b][i]
         if (L < NCG) {
             const int b = L % NG, c = L / NG;

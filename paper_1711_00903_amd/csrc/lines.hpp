@@ -173,4 +173,53 @@ __device__ __forceinline__ void deriv_half_tables(const double *__restrict__ Dgl
         }
 }
 
+// The same half tables in LDS, for Nq beyond what the registers hold next to
+// the lines.  Thread t of the workgroup fetches the pair of FP64 entries
+// behind half-table entry t (the fetch goes out with the element's own loads
+// and is waited for on its own), then stores the entry; the caller
+// synchronises the workgroup before the tables are read.
+template <int NQ>
+__device__ __forceinline__ void interp_pair_load(const double *__restrict__ I1d, int t, double &v0, double &v1)
+{
+    constexpr int HG = (NQ + 2) / 2, HQ = (NQ + 1) / 2;
+    const int tt = t < HG * HQ ? t : 0;
+    const int a = tt / HQ, m = tt - a * HQ;
+    v0 = I1d[a * NQ + m];
+    v1 = I1d[a * NQ + NQ - 1 - m];
+}
+
+template <int NQ, class TC>
+__device__ __forceinline__ void interp_pair_store(TC (*Ie)[(NQ + 1) / 2], TC (*Io)[NQ / 2 > 0 ? NQ / 2 : 1], int t,
+                                                  double v0, double v1)
+{
+    constexpr int NG = NQ + 1, HG = (NG + 1) / 2, HQ = (NQ + 1) / 2, GE = NG / 2, QE = NQ / 2;
+    if (t < HG * HQ) {
+        const int a = t / HQ, m = t - a * HQ;
+        Ie[a][m] = static_cast<TC>(m == NQ - 1 - m ? v0 : 0.5 * (v0 + v1));
+        if (a < GE && m < QE) Io[a][m] = static_cast<TC>(0.5 * (v0 - v1));
+    }
+}
+
+template <int NG>
+__device__ __forceinline__ void deriv_pair_load(const double *__restrict__ Dgl, int t, double &v0, double &v1)
+{
+    constexpr int HG = (NG + 1) / 2;
+    const int tt = t < HG * HG ? t : 0;
+    const int a = tt / HG, m = tt - a * HG;
+    v0 = Dgl[a * NG + m];
+    v1 = Dgl[a * NG + NG - 1 - m];
+}
+
+template <int NG, class TC>
+__device__ __forceinline__ void deriv_pair_store(TC (*Dp)[(NG + 1) / 2], TC (*Dm)[NG / 2 > 0 ? NG / 2 : 1], int t,
+                                                 double v0, double v1)
+{
+    constexpr int GE = NG / 2, HG = (NG + 1) / 2;
+    if (t < HG * HG) {
+        const int a = t / HG, m = t - a * HG;
+        if (a < GE) Dp[a][m] = static_cast<TC>(m == NG - 1 - m ? v0 : 0.5 * (v0 + v1));
+        if (m < GE) Dm[a][m] = static_cast<TC>(0.5 * (v0 - v1));
+    }
+}
+
 }  // namespace fem

@@ -4,9 +4,9 @@
 // line of nodes along t) and packs `epb` elements into one workgroup.  BP3.5
 // works on the Nq x Nq GLL columns; BP1.0 and BP3.0 on the Ng x Ng GL columns
 // (the GLL phases use a subset of those threads).  Exceptions: with one element
-// per workgroup, BP1.0 and BP3.0 (Nq <= 12) run the line-per-lane even-odd
-// kernels of bp10t.hpp (one lane per GLL column) and bp30t.hpp (one lane per
-// Gauss column).
+// per workgroup, BP1.0 and BP3.0 run the line-per-lane even-odd kernels of
+// bp10t.hpp (one lane per GLL column) and bp30t.hpp (one lane per Gauss
+// column).
 #pragma once
 
 #include <array>
@@ -32,9 +32,16 @@ constexpr int bp30_slot_values(int nq, int bytes)
     return r1 + r2 + ng * ng * pg;
 }
 
-// BP1.0 with one element per workgroup and Nq <= 12 runs the line-per-lane
-// kernel (bp10t.hpp): ceil(Nq^2 / 64) waves, one for Nq <= 8.
-constexpr bool bp10_wave(int nq, int epb) { return epb == 1 && nq <= 12; }
+// BP1.0 with one element per workgroup runs the line-per-lane kernel
+// (bp10t.hpp): ceil(Nq^2 / 64) waves, one for Nq <= 8.
+constexpr bool bp10_wave(int nq, int epb) { return epb == 1; }
+
+// Values of the interpolation half tables (LDS copies at high Nq).
+constexpr int interp_half_values(int nq)
+{
+    const int ng = nq + 1;
+    return ((ng + 1) / 2) * ((nq + 1) / 2) + (ng / 2) * (nq / 2 > 0 ? nq / 2 : 1);
+}
 
 constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 {
@@ -42,17 +49,19 @@ constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
     const int p = lds_row(nq, bytes);
     const int av = ng * nq * p;                                       // [c][j][i] volume
     const int wv = (ng * ng * ng * gbytes + 8 + bytes - 1) / bytes;   // staged scaled Jacobians
-    return ((av > wv ? av : wv) + ng * ng * p) * bytes;
+    const int tab = nq >= 12 ? interp_half_values(nq) : 0;   // LDS tables (an upper bound at Nq = 12)
+    return ((av > wv ? av : wv) + ng * ng * p + tab) * bytes;
 }
 
-// BP3.0 with one element per workgroup and Nq <= 12 runs the line-per-lane
-// kernel (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes.
-constexpr bool bp30_line(int nq, int epb) { return epb == 1 && nq <= 12; }
+// BP3.0 with one element per workgroup runs the line-per-lane kernel
+// (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes.
+constexpr bool bp30_line(int nq, int epb) { return epb == 1; }
 
 constexpr int bp30t_lds_bytes(int nq, int bytes)
 {
     const int ng = nq + 1;
-    return 3 * ng * ng * lds_row(ng, bytes) * bytes;
+    const int tab = nq >= 11 ? interp_half_values(nq) + 2 * ((ng + 1) / 2) * (ng / 2) : 0;   // LDS tables
+    return (3 * ng * ng * lds_row(ng, bytes) + tab) * bytes;
 }
 
 // LDS bytes of one workgroup for values of `bytes` bytes (tables included);
@@ -98,8 +107,8 @@ constexpr std::array<int, 4> epb_choices(int op, int nq)
 // else the smallest packing that does.
 constexpr int epb_default(int op, int nq)
 {
-    if (op == 0 && nq >= 5 && nq <= 12) return 1;  // the line-per-lane BP1.0 kernel (measured fastest, N = 4..11)
-    if (op == 2 && nq >= 4 && nq <= 12) return 1;  // the line-per-lane BP3.0 kernel (FP64, N = 3..11)
+    if (op == 0 && nq >= 5) return 1;  // the line-per-lane BP1.0 kernel (measured fastest, N = 4..15)
+    if (op == 2 && nq >= 4) return 1;  // the line-per-lane BP3.0 kernel (FP64, N = 3..15)
     const int cols = columns(op, nq);
     if (cols * 5 >= round_up_wave(cols) * 4) return 1;
     const auto ch = epb_choices(op, nq);

@@ -73,14 +73,13 @@ def test_tune_table(fem):
                 th, lds = fem.fem_kernel_info(op, N, fem.FEM_F64, c)
                 assert th % 64 == 0 and 64 <= th <= 512
                 assert 0 < lds <= 160 * 1024
-    # BP1.0 with one element per workgroup runs the line-per-lane kernel up to
-    # N = 11 (one lane per GLL column: one wave up to N = 7)
+    # BP1.0 with one element per workgroup runs the line-per-lane kernel (one
+    # lane per GLL column: one wave up to N = 7); BP3.0 one lane per Gauss column
     for N in range(1, 16):
         th, _ = fem.fem_kernel_info(fem.FEM_OP_BP10, N, fem.FEM_F64, 1)
-        if N <= 11:
-            assert th == (N + 1) ** 2 + (-(N + 1) ** 2) % 64, (N, th)
-        else:
-            assert th == (N + 2) ** 2 + (-(N + 2) ** 2) % 64, (N, th)
+        assert th == (N + 1) ** 2 + (-(N + 1) ** 2) % 64, (N, th)
+        th, _ = fem.fem_kernel_info(fem.FEM_OP_BP30, N, fem.FEM_F64, 1)
+        assert th == (N + 2) ** 2 + (-(N + 2) ** 2) % 64, (N, th)
     fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 2, 1024)
     assert fem.fem_tune_get(fem.FEM_OP_BP35, 7, fem.FEM_F64) == (2, 1024)
     fem.fem_tune_set(fem.FEM_OP_BP35, 7, fem.FEM_F64, 0, 0)

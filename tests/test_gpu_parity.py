@@ -140,7 +140,7 @@ def test_operator_parity_all_degrees(fem, DeviceMesh, op, N, epb):
 
 
 @pytest.mark.parametrize("op", ["BP35", "BP30"])
-@pytest.mark.parametrize("N", [2, 7, 11])
+@pytest.mark.parametrize("N", [2, 7, 11, 14])
 def test_lambda_and_beta(fem, DeviceMesh, op, N):
     X, n = mesh_elems(40)
     E = X.shape[0]
