@@ -38,9 +38,11 @@ BENCH_WORKLOADS = {
 }
 # the sources whose hash must match the committed HBM counters of a workload
 KERNEL_SOURCES = {
-    "BP35": ["bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
-    "BP10": ["bp10.hpp", "bp10t.hpp", "lines.hpp", "bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
-    "BP30": ["bp30.hpp", "bp30t.hpp", "lines.hpp", "bp35.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
+    "BP35": ["bp35.hpp", "bp35t.hpp", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
+    "BP10": ["bp10.hpp", "bp10t.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
+             "launch.hpp"],
+    "BP30": ["bp30.hpp", "bp30t.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
+             "launch.hpp"],
 }
 OP_LABEL = {"BP10": "BP1.0", "BP35": "BP3.5", "BP30": "BP3.0"}
 

@@ -8,6 +8,7 @@
 // after u is staged, and after the weighted gradients (wr, ws) are staged.
 #pragma once
 
+#include "bp35t.hpp"
 #include "fem_device.hpp"
 #include "launch.hpp"
 #include "tiles.hpp"
@@ -354,6 +355,11 @@ hipError_t bp35_launch_nq(const ApplyArgs &a, hipStream_t s)
 {
     constexpr auto ch = epb_choices(1, NQ);
     const int epb = a.epb > 0 ? a.epb : epb_default(1, NQ);
+    // one element per workgroup at high degree: the line-per-lane kernel (the
+    // direction update of the conjugate-gradient split stays on the column kernel)
+    if constexpr (bp35_line(NQ, 1)) {
+        if (epb == 1 && !a.xr) return bp35t_launch_t<NQ, TG, TV>(a, s);
+    }
     if (epb == ch[0]) return bp35_launch_t<NQ, ch[0], TG, TV>(a, s);
     if constexpr (ch[1] > 0) if (epb == ch[1]) return bp35_launch_t<NQ, ch[1], TG, TV>(a, s);
     if constexpr (ch[2] > 0) if (epb == ch[2]) return bp35_launch_t<NQ, ch[2], TG, TV>(a, s);

@@ -6,7 +6,7 @@
 // (the GLL phases use a subset of those threads).  Exceptions: with one element
 // per workgroup, BP1.0 and BP3.0 run the line-per-lane even-odd kernels of
 // bp10t.hpp (one lane per GLL column) and bp30t.hpp (one lane per Gauss
-// column).
+// column), and BP3.5 at Nq >= 11 that of bp35t.hpp.
 #pragma once
 
 #include <array>
@@ -64,6 +64,15 @@ constexpr int bp30t_lds_bytes(int nq, int bytes)
     return (3 * ng * ng * lds_row(ng, bytes) + tab) * bytes;
 }
 
+// BP3.5 with one element per workgroup and Nq >= 11 runs the line-per-lane
+// kernel (bp35t.hpp): two Nq^3 LDS volumes and the derivative half tables.
+constexpr bool bp35_line(int nq, int epb) { return epb == 1 && nq >= 11; }
+
+constexpr int bp35t_lds_bytes(int nq, int bytes)
+{
+    return (2 * nq * nq * lds_row(nq, bytes) + 2 * ((nq + 1) / 2) * (nq / 2)) * bytes;
+}
+
 // LDS bytes of one workgroup for values of `bytes` bytes (tables included);
 // gbytes: stored size of a geometric value (BP1.0 one-wave staging).
 constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
@@ -72,6 +81,7 @@ constexpr int lds_bytes(int op, int nq, int epb, int bytes, int gbytes = 8)
     const int pq = lds_row(nq, bytes), pg = lds_row(ng, bytes);
     if (op == 0 && bp10_wave(nq, epb)) return bp10t_lds_bytes(nq, bytes, gbytes);
     if (op == 2 && bp30_line(nq, epb)) return bp30t_lds_bytes(nq, bytes);
+    if (op == 1 && bp35_line(nq, epb)) return bp35t_lds_bytes(nq, bytes);
     if (op == 1) return (nq * nq + 3 * epb * nq * nq * pq) * bytes;
     if (op == 0) {
         const int slot = nq * nq * pq + nq * nq * pg + nq * ng * pg;
