@@ -203,6 +203,26 @@ def test_grid_cap_persistent_loop(fem, DeviceMesh):
             fem.fem_tune_set(opid, N, 0, 0, 0)
 
 
+def test_grid_cap_line_kernels_high_degree(fem, DeviceMesh):
+    """The line-per-lane kernels at high degree (half tables in LDS) split a
+    capped grid over several launches: same result, ragged last launch."""
+    N = 12
+    X, n = mesh_elems(60)
+    E = X.shape[0]
+    u = workloads.field(E, N + 1, seed=13)
+    dev = DeviceMesh(N, X, h=1.0 / n)
+    ut = torch.from_numpy(u).cuda()
+    for op in ("BP10", "BP35", "BP30"):
+        opid = fem.OP_NAMES[op]
+        try:
+            fem.fem_tune_set(opid, N, 0, 1, 7)
+            y = gpu_apply(dev, op, ut)
+            torch.cuda.synchronize()
+            compare(y, oracle_apply(op, N, X, u), f"{op} N={N} epb=1 capped grid")
+        finally:
+            fem.fem_tune_set(opid, N, 0, 0, 0)
+
+
 # ---------------------------------------------------------------- reduced precision
 
 # Error of storage-rounded inputs with FP32 arithmetic, against the FP64 oracle.
