@@ -140,6 +140,24 @@ int fem_stiff_collocated_apply(int N, int64_t E, const double *D1d, const void *
                                double lambda, const void *u, void *y, double beta, int prec,
                                float geo_scale, void *stream);
 
+/* DEVICE.  BP3.5 (Alg. 4) in FP64 with the geometric factors evaluated in the
+ * kernel, per GLL point, from the element's trilinear map instead of read from
+ * G and wJ: the BP3.5 optimisation section weighs loading the factors against
+ * computing them from the vertices, and loads them.  Applies the same operator
+ * as fem_stiff_collocated_apply with the G and wJ that fem_geometric_factors
+ * (FEM_QUAD_GLL, FEM_F64) writes for X, up to rounding, while moving only the
+ * fields (16 B per point instead of 64 B).
+ *   y = (D^T G D + lambda J) u + beta y      (beta == 0: y is not read)
+ * X[e][a+2b+4c][0..2]: the 8 vertices of element e (FP64, as for
+ * fem_geometric_factors); D1d, u, y as for fem_stiff_collocated_apply with
+ * prec = FEM_F64.  All are device pointers owned by the caller, 16-byte
+ * aligned; u != y.  FEM_ERR_ARG for N outside [1, 15], E < 0 or beyond the
+ * element limit, a NULL pointer or u == y; FEM_ERR_ALIGN for a misaligned
+ * pointer; nothing is enqueued then.  Asynchronous on the stream; E == 0 is a
+ * no-op. */
+int fem_stiff_collocated_vertex_apply(int N, int64_t E, const double *D1d, const double *X, double lambda,
+                                      const double *u, double *y, double beta, void *stream);
+
 /* DEVICE.  BP3.0 de-aliased screened-Poisson operator, Alg. 5:
  * y = I^T (D~^T G D~ + lambda J) I u + beta y, G and wJ at GL nodes.  wJ may be
  * NULL iff lambda == 0. */

@@ -95,6 +95,8 @@ _SIGS = {
                        C.c_int),
     "fem_stiff_collocated_apply": ([C.c_int, _i64, _vp, _vp, _vp, C.c_double, _vp, _vp, C.c_double,
                                     C.c_int, C.c_float, _vp], C.c_int),
+    "fem_stiff_collocated_vertex_apply": ([C.c_int, _i64, _vp, _vp, C.c_double, _vp, _vp, C.c_double, _vp],
+                                          C.c_int),
     "fem_stiff_dealiased_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp,
                                    C.c_double, C.c_int, C.c_float, _vp], C.c_int),
     "fem_stream_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
@@ -237,6 +239,11 @@ def fem_stiff_collocated_apply(N, E, D1d, G, wJ, lam, u, y, beta=0.0, prec=FEM_F
     _check(lib().fem_stiff_collocated_apply(N, E, _ptr(D1d), _ptr(G), _ptr(wJ), lam, _ptr(u), _ptr(y),
                                             beta, prec, geo_scale, _stream(stream)),
            "fem_stiff_collocated_apply")
+
+
+def fem_stiff_collocated_vertex_apply(N, E, D1d, X, lam, u, y, beta=0.0, stream=None) -> None:
+    _check(lib().fem_stiff_collocated_vertex_apply(N, E, _ptr(D1d), _ptr(X), lam, _ptr(u), _ptr(y), beta,
+                                                   _stream(stream)), "fem_stiff_collocated_vertex_apply")
 
 
 def fem_stiff_dealiased_apply(N, E, I1d, Dgl, G, wJ, lam, u, y, beta=0.0, prec=FEM_F64,

@@ -117,6 +117,14 @@ def test_validation_rejects_before_enqueue(fem):
          fem.FEM_ERR_ARG),
         (lambda: fem.fem_geometric_factors(7, 4, 2, bad, bad, bad, stream=0), fem.FEM_ERR_ARG),
         (lambda: fem.fem_geometric_factors(7, 4, 0, bad, None, None, stream=0), fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_collocated_vertex_apply(0, 4, bad, bad, 0.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_collocated_vertex_apply(7, 4, bad, None, 0.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_collocated_vertex_apply(7, 4, bad, bad, 0.0, bad, bad, stream=0),
+         fem.FEM_ERR_ARG),   # u == y
+        (lambda: fem.fem_stiff_collocated_vertex_apply(7, 4, bad, bad + 8, 0.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ALIGN),
         (lambda: fem.fem_stream_copy(bad, 1 << 40, 17, stream=0), fem.FEM_ERR_ARG),
         (lambda: fem.fem_stream_copy(bad, bad + 16, 64, stream=0), fem.FEM_ERR_ARG),
     ]
@@ -131,6 +139,7 @@ def test_empty_calls_are_noops(fem):
     fem.fem_mass_apply(3, 0, None, None, None, None, stream=0)
     fem.fem_stiff_dealiased_apply(5, 0, None, None, None, None, 0.0, None, None, stream=0)
     fem.fem_stream_copy(None, None, 0, stream=0)
+    fem.fem_stiff_collocated_vertex_apply(7, 0, None, None, 0.0, None, None, stream=0)
 
 
 def test_cg_struct_layout_matches_header(fem, tmp_path):

@@ -223,6 +223,30 @@ def test_grid_cap_line_kernels_high_degree(fem, DeviceMesh):
             fem.fem_tune_set(opid, N, 0, 0, 0)
 
 
+@pytest.mark.parametrize("N", [1, 3, 7, 10, 15])
+def test_vertex_geometry_stiffness(fem, DeviceMesh, N):
+    """BP3.5 with the factors formed in the kernel from the vertices: the
+    oracle's operator (factors from the same trilinear map), with lambda and
+    beta, and the stored-factor kernel on the same input."""
+    X, n = mesh_elems(30)
+    E = X.shape[0]
+    u = workloads.field(E, N + 1, seed=21)
+    y0 = workloads.field(E, N + 1, seed=22)
+    dev = DeviceMesh(N, X, h=1.0 / n)
+    ut = torch.from_numpy(u).cuda()
+    y = dev.stiff35_vertices(ut)
+    torch.cuda.synchronize()
+    compare(y, oracle_apply("BP35", N, X, u), f"BP35 vertices N={N}")
+    ys = dev.stiff35(ut)
+    torch.cuda.synchronize()
+    compare(y, ys.cpu().numpy(), f"BP35 vertices vs stored factors N={N}")
+    lam, beta = 0.75, -0.5
+    yt = torch.from_numpy(y0).cuda()
+    dev.stiff35_vertices(ut, y=yt, lam=lam, beta=beta)
+    torch.cuda.synchronize()
+    compare(yt, oracle_apply("BP35", N, X, u, lam) + beta * y0, f"BP35 vertices lambda/beta N={N}")
+
+
 # ---------------------------------------------------------------- reduced precision
 
 # Error of storage-rounded inputs with FP32 arithmetic, against the FP64 oracle.
