@@ -29,8 +29,13 @@ struct GllRule {
 
 constexpr int bp35v_threads(int nq) { return round_up_wave(nq * nq); }
 
+// Waves per SIMD asked of the register allocator: three up to Nq = 6, where
+// that spills nothing (N = 5: +7%); at Nq = 7, 8 it would spill and was slower.
+constexpr int bp35v_min_waves(int nq) { return nq <= 6 ? 3 : 1; }
+
 template <int NQ>
-__global__ __launch_bounds__(bp35v_threads(NQ)) void bp35v_kernel(const double *__restrict__ D1d,
+__global__ __launch_bounds__(bp35v_threads(NQ))
+__attribute__((amdgpu_waves_per_eu(bp35v_min_waves(NQ)))) void bp35v_kernel(const double *__restrict__ D1d,
                                                                   const double *__restrict__ X, GllRule rule,
                                                                   double lambda, const double *__restrict__ u,
                                                                   double *__restrict__ y, double beta, int64_t e0)
