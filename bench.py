@@ -37,6 +37,8 @@ BENCH_WORKLOADS = {
     "bp30_n7_e262144": ("BP30", 7, 64),
     # BP3.5 with the geometric factors formed in the kernel from the vertices
     "bp35v_n7_e32768": ("BP35V", 7, 32),
+    # BP3.0 likewise (factors at the Gauss points from the vertices)
+    "bp30v_n7_e262144": ("BP30V", 7, 64),
 }
 # the sources whose hash must match the committed HBM counters of a workload
 KERNEL_SOURCES = {
@@ -46,8 +48,10 @@ KERNEL_SOURCES = {
     "BP30": ["bp30.hpp", "bp30t.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
              "launch.hpp"],
     "BP35V": ["bp35v.hip", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
+    "BP30V": ["bp30v.hip", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
 }
-OP_LABEL = {"BP10": "BP1.0", "BP35": "BP3.5", "BP30": "BP3.0", "BP35V": "BP3.5 (factors from vertices)"}
+OP_LABEL = {"BP10": "BP1.0", "BP35": "BP3.5", "BP30": "BP3.0", "BP35V": "BP3.5 (factors from vertices)",
+            "BP30V": "BP3.0 (factors from vertices)"}
 FP64_PEAK_TFLOPS = 78.6
 # FP64 flops per GLL point of the in-kernel factors (BP3.5 from vertices): a_r and
 # a_s (12), three cross products (27), |J| (5), weights and 1/|J| (3), six dot
@@ -116,7 +120,7 @@ def cpu_baseline(op: str, Nb: int, X, u, budget_s: float) -> dict:
     threads = oracle.set_threads(0)
     E = X.shape[0]
     pb = oracle.Problem(Nb, X[:min(E, 16384)])
-    apply = {"BP10": pb.mass, "BP35": pb.stiff35, "BP35V": pb.stiff35, "BP30": pb.stiff30}[op]
+    apply = {"BP10": pb.mass, "BP35": pb.stiff35, "BP35V": pb.stiff35, "BP30": pb.stiff30, "BP30V": pb.stiff30}[op]
     apply(u[:min(E, 8)])   # geometry built outside the timing
     # size the sample so that one pass takes ~1/5 of the budget
     Es = min(E, 512)
@@ -381,7 +385,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     workload = args.workload
     op, Nb, grid = BENCH_WORKLOADS[workload]
-    opid = fem.OP_NAMES[op] if op != "BP35V" else None
+    opid = fem.OP_NAMES[op] if op in fem.OP_NAMES else None
     if opid is not None and (args.epb or args.grid_cap):
         fem.fem_tune_set(opid, Nb, fem.FEM_F64, args.epb, args.grid_cap)
 
@@ -401,6 +405,9 @@ def main() -> int:
     elif op == "BP35V":
         def step():
             fem.fem_stiff_collocated_vertex_apply(Nb, E, dev.D1d, dev.X, 0.0, ut, y, 0.0, stream)
+    elif op == "BP30V":
+        def step():
+            fem.fem_stiff_dealiased_vertex_apply(Nb, E, dev.I1d, dev.Dgl, dev.X, 0.0, ut, y, 0.0, stream)
     elif op == "BP10":
         _, wJ = dev.geometry(fem.FEM_QUAD_GL, want_G=False, kind="wJ")
 
@@ -439,7 +446,7 @@ def main() -> int:
         epb = fem.fem_tune_get(opid, Nb, fem.FEM_F64)[0] or fem.fem_supported_epb(opid, Nb, fem.FEM_F64)[0]
     dofs = E * (Nb + 1) ** 3
     # algorithmic bytes: u and y once, plus the stored factors (or the 8 vertices)
-    bytes_launch = (16 * dofs + 192 * E) if op == "BP35V" else tune.alg_bytes(op, Nb, E, fem.FEM_F64)
+    bytes_launch = (16 * dofs + 192 * E) if op in ("BP35V", "BP30V") else tune.alg_bytes(op, Nb, E, fem.FEM_F64)
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
     copy = copy_roofline(fem, torch, bytes_launch)
     log(f"bench: copy roofline {copy}")
@@ -451,6 +458,7 @@ def main() -> int:
 
     kname = {"BP35": f"bp35_kernel<{Nb + 1},{epb},double,double>",
              "BP35V": f"bp35v_kernel<{Nb + 1}>",
+             "BP30V": f"bp30v_kernel<{Nb + 1},double,double>",
              "BP10": f"bp10t_kernel<{Nb + 1},double,double>" if epb == 1 and Nb <= 7
              else f"bp10_kernel<{Nb + 1},{epb},double,double>",
              "BP30": f"bp30t_kernel<{Nb + 1},double,double>" if epb == 1 and Nb <= 7
@@ -482,9 +490,10 @@ def main() -> int:
                           "frac_of_copy": achieved / copy["best"]},
         "cpu_baseline": cpu,
     }
-    if op == "BP35V":
+    if op in ("BP35V", "BP30V"):
         # the factors are computed, not read: FP64 arithmetic is the bound to price against
-        flops = E * (tune.alg_flops("BP35", Nb, 1) + VERTEX_GEO_FLOPS * (Nb + 1) ** 3)
+        npts = (Nb + 1) ** 3 if op == "BP35V" else (Nb + 2) ** 3
+        flops = E * (tune.alg_flops(op[:4], Nb, 1) + VERTEX_GEO_FLOPS * npts)
         tf = flops / (kern_ms * 1e-3) / 1e12
         rec["config"]["factors"] = "from vertices"
         rec["roofline"] = {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -158,6 +158,19 @@ int fem_stiff_collocated_apply(int N, int64_t E, const double *D1d, const void *
 int fem_stiff_collocated_vertex_apply(int N, int64_t E, const double *D1d, const double *X, double lambda,
                                       const double *u, double *y, double beta, void *stream);
 
+/* DEVICE.  BP3.0 (Alg. 5) in FP64 with the geometric factors evaluated in the
+ * kernel, per Gauss point, from the element's trilinear map instead of read
+ * from G and wJ (the load-or-recompute trade of the BP3.5 optimisation
+ * section, for the operator whose factors are 81% of its bytes at N = 7).
+ * Applies the same operator as fem_stiff_dealiased_apply with the G and wJ
+ * that fem_geometric_factors (FEM_QUAD_GL, FEM_F64) writes for X, up to
+ * rounding.  X as for fem_stiff_collocated_vertex_apply; I1d, Dgl, u, y as for
+ * fem_stiff_dealiased_apply with prec = FEM_F64.  Device pointers owned by the
+ * caller, 16-byte aligned, u != y; errors and asynchrony as for
+ * fem_stiff_collocated_vertex_apply. */
+int fem_stiff_dealiased_vertex_apply(int N, int64_t E, const double *I1d, const double *Dgl, const double *X,
+                                     double lambda, const double *u, double *y, double beta, void *stream);
+
 /* DEVICE.  BP3.0 de-aliased screened-Poisson operator, Alg. 5:
  * y = I^T (D~^T G D~ + lambda J) I u + beta y, G and wJ at GL nodes.  wJ may be
  * NULL iff lambda == 0. */

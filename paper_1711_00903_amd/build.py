@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfem.so")
 
 PRECS = ["f64", "f32", "bf16", "f16", "bf16g", "f16g", "f32g64", "bf16g64", "f16g64"]
-SOURCES = ["fem_api.cpp", "batch.cpp", "basis.cpp", "geometry.hip", "cg.hip", "bp35v.hip",
+SOURCES = ["fem_api.cpp", "batch.cpp", "basis.cpp", "geometry.hip", "cg.hip", "bp35v.hip", "bp30v.hip",
            "cgop_f64.hip", "cgop_f32g64.hip", "cgop_bf16g64.hip", "cgop_f16g64.hip"] + [
     f"{op}_{p}.hip" for op in ("bp35", "bp10", "bp30") for p in PRECS]
 

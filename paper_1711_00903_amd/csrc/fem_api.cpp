@@ -18,6 +18,8 @@ namespace fem {
 
 hipError_t launch_bp35v(int N, int64_t E, const double *D1d, const double *X, double lambda, const double *u,
                         double *y, double beta, int64_t grid_cap, hipStream_t s);
+hipError_t launch_bp30v(int N, int64_t E, const double *I1d, const double *Dgl, const double *X, double lambda,
+                        const double *u, double *y, double beta, hipStream_t s);
 hipError_t launch_bp35_f64(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp35_f32(const ApplyArgs &, hipStream_t);
 hipError_t launch_bp35_bf16(const ApplyArgs &, hipStream_t);
@@ -380,6 +382,17 @@ int fem_stiff_collocated_vertex_apply(int N, int64_t E, const double *D1d, const
     if (!D1d || !X || !u || !y || static_cast<const void *>(u) == static_cast<const void *>(y)) return FEM_ERR_ARG;
     if (!aligned16(D1d) || !aligned16(X) || !aligned16(u) || !aligned16(y)) return FEM_ERR_ALIGN;
     return finish(launch_bp35v(N, E, D1d, X, lambda, u, y, beta, 0, static_cast<hipStream_t>(stream)));
+}
+
+int fem_stiff_dealiased_vertex_apply(int N, int64_t E, const double *I1d, const double *Dgl, const double *X,
+                                     double lambda, const double *u, double *y, double beta, void *stream)
+{
+    if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
+    if (E == 0) return FEM_OK;
+    if (!I1d || !Dgl || !X || !u || !y || static_cast<const void *>(u) == static_cast<const void *>(y))
+        return FEM_ERR_ARG;
+    if (!aligned16(I1d) || !aligned16(Dgl) || !aligned16(X) || !aligned16(u) || !aligned16(y)) return FEM_ERR_ALIGN;
+    return finish(launch_bp30v(N, E, I1d, Dgl, X, lambda, u, y, beta, static_cast<hipStream_t>(stream)));
 }
 
 int fem_stiff_dealiased_apply(int N, int64_t E, const double *I1d, const double *Dgl, const void *G,

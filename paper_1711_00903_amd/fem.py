@@ -97,6 +97,8 @@ _SIGS = {
                                     C.c_int, C.c_float, _vp], C.c_int),
     "fem_stiff_collocated_vertex_apply": ([C.c_int, _i64, _vp, _vp, C.c_double, _vp, _vp, C.c_double, _vp],
                                           C.c_int),
+    "fem_stiff_dealiased_vertex_apply": ([C.c_int, _i64, _vp, _vp, _vp, C.c_double, _vp, _vp, C.c_double,
+                                          _vp], C.c_int),
     "fem_stiff_dealiased_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp,
                                    C.c_double, C.c_int, C.c_float, _vp], C.c_int),
     "fem_stream_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
@@ -244,6 +246,11 @@ def fem_stiff_collocated_apply(N, E, D1d, G, wJ, lam, u, y, beta=0.0, prec=FEM_F
 def fem_stiff_collocated_vertex_apply(N, E, D1d, X, lam, u, y, beta=0.0, stream=None) -> None:
     _check(lib().fem_stiff_collocated_vertex_apply(N, E, _ptr(D1d), _ptr(X), lam, _ptr(u), _ptr(y), beta,
                                                    _stream(stream)), "fem_stiff_collocated_vertex_apply")
+
+
+def fem_stiff_dealiased_vertex_apply(N, E, I1d, Dgl, X, lam, u, y, beta=0.0, stream=None) -> None:
+    _check(lib().fem_stiff_dealiased_vertex_apply(N, E, _ptr(I1d), _ptr(Dgl), _ptr(X), lam, _ptr(u), _ptr(y),
+                                                  beta, _stream(stream)), "fem_stiff_dealiased_vertex_apply")
 
 
 def fem_stiff_dealiased_apply(N, E, I1d, Dgl, G, wJ, lam, u, y, beta=0.0, prec=FEM_F64,

@@ -133,6 +133,13 @@ class DeviceMesh:
         fem.fem_stiff_collocated_vertex_apply(self.N, self.E, self.D1d, self.X, lam, u, y, beta, stream)
         return y
 
+    def stiff30_vertices(self, u, y=None, lam=0.0, beta=0.0, stream=None):
+        """BP3.0 in FP64 with the geometric factors formed in the kernel from
+        the element vertices (no G or wJ in memory)."""
+        y = self._y(y, fem.FEM_F64)
+        fem.fem_stiff_dealiased_vertex_apply(self.N, self.E, self.I1d, self.Dgl, self.X, lam, u, y, beta, stream)
+        return y
+
     def stiff30(self, u, y=None, lam=0.0, beta=0.0, prec=fem.FEM_F64, stream=None):
         G, _ = self.geometry(fem.FEM_QUAD_GL, prec, want_wJ=False)
         wJ = self.geometry(fem.FEM_QUAD_GL, prec, want_G=False)[1] if lam else None

@@ -125,6 +125,10 @@ def test_validation_rejects_before_enqueue(fem):
          fem.FEM_ERR_ARG),   # u == y
         (lambda: fem.fem_stiff_collocated_vertex_apply(7, 4, bad, bad + 8, 0.0, bad, 1 << 40, stream=0),
          fem.FEM_ERR_ALIGN),
+        (lambda: fem.fem_stiff_dealiased_vertex_apply(16, 4, bad, bad, bad, 0.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ARG),
+        (lambda: fem.fem_stiff_dealiased_vertex_apply(7, 4, bad, bad, bad + 8, 0.0, bad, 1 << 40, stream=0),
+         fem.FEM_ERR_ALIGN),
         (lambda: fem.fem_stream_copy(bad, 1 << 40, 17, stream=0), fem.FEM_ERR_ARG),
         (lambda: fem.fem_stream_copy(bad, bad + 16, 64, stream=0), fem.FEM_ERR_ARG),
     ]

@@ -247,6 +247,29 @@ def test_vertex_geometry_stiffness(fem, DeviceMesh, N):
     compare(yt, oracle_apply("BP35", N, X, u, lam) + beta * y0, f"BP35 vertices lambda/beta N={N}")
 
 
+@pytest.mark.parametrize("N", [1, 3, 7, 10, 15])
+def test_vertex_geometry_dealiased(fem, DeviceMesh, N):
+    """BP3.0 with the factors formed in the kernel from the vertices: the
+    oracle's operator, with lambda and beta, and the stored-factor kernel."""
+    X, n = mesh_elems(30)
+    E = X.shape[0]
+    u = workloads.field(E, N + 1, seed=23)
+    y0 = workloads.field(E, N + 1, seed=24)
+    dev = DeviceMesh(N, X, h=1.0 / n)
+    ut = torch.from_numpy(u).cuda()
+    y = dev.stiff30_vertices(ut)
+    torch.cuda.synchronize()
+    compare(y, oracle_apply("BP30", N, X, u), f"BP30 vertices N={N}")
+    ys = dev.stiff30(ut)
+    torch.cuda.synchronize()
+    compare(y, ys.cpu().numpy(), f"BP30 vertices vs stored factors N={N}")
+    lam, beta = 0.75, -0.5
+    yt = torch.from_numpy(y0).cuda()
+    dev.stiff30_vertices(ut, y=yt, lam=lam, beta=beta)
+    torch.cuda.synchronize()
+    compare(yt, oracle_apply("BP30", N, X, u, lam) + beta * y0, f"BP30 vertices lambda/beta N={N}")
+
+
 # ---------------------------------------------------------------- reduced precision
 
 # Error of storage-rounded inputs with FP32 arithmetic, against the FP64 oracle.
