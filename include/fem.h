@@ -91,6 +91,13 @@ const char *fem_status_str(int status);
 /* Library version, major*10000 + minor*100 + patch. */
 int fem_version(void);
 
+/* Identity of the sources the library was built from: the first 16 hex
+ * digits of a SHA-256 over the names and contents of the kernel and ABI
+ * sources and of this header, taken at build time (static string; "unknown"
+ * for a build that did not supply it).  Lets a caller detect a library that
+ * is stale against its sources. */
+const char *fem_build_id(void);
+
 /* Maximum supported degree N (15). */
 int fem_max_degree(void);
 
@@ -151,10 +158,10 @@ int fem_stiff_collocated_apply(int N, int64_t E, const double *D1d, const void *
  * X[e][a+2b+4c][0..2]: the 8 vertices of element e (FP64, as for
  * fem_geometric_factors); D1d, u, y as for fem_stiff_collocated_apply with
  * prec = FEM_F64.  All are device pointers owned by the caller, 16-byte
- * aligned; u != y.  FEM_ERR_ARG for N outside [1, 15], E < 0 or beyond the
- * element limit, a NULL pointer or u == y; FEM_ERR_ALIGN for a misaligned
- * pointer; nothing is enqueued then.  Asynchronous on the stream; E == 0 is a
- * no-op. */
+ * aligned; u and y must not overlap.  FEM_ERR_ARG for N outside [1, 15],
+ * E < 0 or beyond the element limit, a NULL pointer or overlapping u and y;
+ * FEM_ERR_ALIGN for a misaligned pointer; nothing is enqueued then.
+ * Asynchronous on the stream; E == 0 is a no-op. */
 int fem_stiff_collocated_vertex_apply(int N, int64_t E, const double *D1d, const double *X, double lambda,
                                       const double *u, double *y, double beta, void *stream);
 
@@ -166,8 +173,8 @@ int fem_stiff_collocated_vertex_apply(int N, int64_t E, const double *D1d, const
  * that fem_geometric_factors (FEM_QUAD_GL, FEM_F64) writes for X, up to
  * rounding.  X as for fem_stiff_collocated_vertex_apply; I1d, Dgl, u, y as for
  * fem_stiff_dealiased_apply with prec = FEM_F64.  Device pointers owned by the
- * caller, 16-byte aligned, u != y; errors and asynchrony as for
- * fem_stiff_collocated_vertex_apply. */
+ * caller, 16-byte aligned, u and y not overlapping; errors and asynchrony as
+ * for fem_stiff_collocated_vertex_apply. */
 int fem_stiff_dealiased_vertex_apply(int N, int64_t E, const double *I1d, const double *Dgl, const double *X,
                                      double lambda, const double *u, double *y, double beta, void *stream);
 
@@ -184,6 +191,16 @@ int fem_stiff_dealiased_apply(int N, int64_t E, const double *I1d, const double 
  * a multiple of 16. */
 int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/* DEVICE.  LDS bandwidth probe, the measured B_sh of the shared-memory
+ * roofline (Empirical performance model section, eq. sharedRoof): each of
+ * `workgroups` workgroups of 256 lanes moves 256 x iters x 16 vectors through
+ * its own 32 KiB of LDS, conflict-free; mode 0: 8-byte reads, 1: 16-byte
+ * reads, 2: 8-byte writes, 3: 16-byte writes.  Bytes moved:
+ * workgroups x 256 x iters x 16 x (8 or 16).  sink: device array of
+ * workgroups x 256 doubles (the lanes' sums, so no access is dead); the
+ * caller times the launch. */
+int fem_lds_bandwidth(int mode, int64_t workgroups, int iters, double *sink, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Conjugate gradients on A = S + lambda M, with S the BP3.5 stiffness (GLL
  * collocation, 6 factors) and M the BP1.0 mass (GL quadrature): symmetric, and
@@ -193,7 +210,10 @@ int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
  * mode 0: FP64 CG.  mode 1: mixed precision -- the Krylov iteration runs with
  * the operator's geometric data stored in `inner_prec`'s geometry type, and
  * FP32 vectors (FEM_F32, FEM_BF16G, FEM_F16G) or FP64 vectors and arithmetic
- * (FEM_F32G64, FEM_BF16G64, FEM_F16G64).  Both modes use reliable updates: whenever the
+ * (FEM_F32G64, FEM_BF16G64, FEM_F16G64).  mode 2: iterative refinement -- as
+ * mode 1, but every reliable update also restarts the Krylov iteration from
+ * the replaced residual, so each refinement step is a fresh inner CG stopped
+ * after reducing the residual by `delta`.  All modes use reliable updates: whenever the
  * recursive residual has dropped by `delta` (default 0.1) relative to the last
  * true residual, the iterate is folded into the FP64 x and r = b - A x is
  * recomputed with the FP64 operator.  The solve stops when the FP64 true
@@ -227,7 +247,8 @@ typedef struct {
 typedef enum { FEM_CG_FUSE_AUTO = 0, FEM_CG_FUSE_NONE = 1, FEM_CG_FUSE_ONEPASS = 2 } fem_cg_fusion;
 
 typedef struct {
-    int mode;                  /* 0 = FP64 CG, 1 = mixed precision                    */
+    int mode;                  /* 0 = FP64 CG, 1 = mixed precision, 2 = mixed         */
+                               /* precision with restarts (iterative refinement)     */
     double rtol;               /* relative FP64 true-residual target                  */
     int max_iters;             /* iterations of the Krylov loop                       */
     double delta;              /* reliable-update threshold, (0, 1); 0 = 0.1          */
@@ -260,6 +281,75 @@ size_t fem_cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *o
  * or during the solve. */
 int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
                  void *workspace, size_t workspace_bytes, fem_cg_report *rep, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Assembled (continuous) operator.  The applies above act on each element's
+ * own copy of its nodes: one block-diagonal matrix (Problem description
+ * section).  On a conforming mesh neighbouring elements share the nodes of
+ * their common faces, edges and corners; with Z the Boolean map that copies
+ * global node values to the element-local nodes, the global finite-element
+ * operator is A = Z^T A_L Z.  Z is given by `gather` ([E][Np], int32: the
+ * global node of each local node, element-major, local node order as for the
+ * fields); Z^T by its inverse, `offsets` ([n_global + 1]) and `locals`
+ * ([E Np]): the local copies of global node g are locals[offsets[g] ..
+ * offsets[g+1] - 1], in ascending order (fem_assembly_inverse_map builds
+ * them).  Z^T sums each node's copies in that order, so results are
+ * repeatable bit for bit.  Index maps are read on the device with every
+ * index checked against its range (an entry out of range reads as zero):
+ * a wrong map gives wrong values, never an access outside the arrays.
+ * Limits: E Np and n_global below 2^31.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n_global;          /* number of global nodes                              */
+    const int32_t *gather;     /* [E][Np] device: global node of each local node      */
+    const int32_t *offsets;    /* [n_global + 1] device                               */
+    const int32_t *locals;     /* [E Np] device: local nodes grouped by global node   */
+} fem_assembly;
+
+/* HOST.  The inverse map of a gather map: offsets [n_global + 1] and locals
+ * [n_local] (host arrays) from gather [n_local] (host).  FEM_ERR_ARG if an
+ * entry of gather lies outside [0, n_global) or a size is out of range. */
+int fem_assembly_inverse_map(int64_t n_local, const int32_t *gather, int64_t n_global, int32_t *offsets,
+                             int32_t *locals);
+
+/* DEVICE.  ul = Z ug: ul[l] = ug[gather[l]], l < n_local. */
+int fem_gather(int64_t n_local, int64_t n_global, const int32_t *gather, const double *ug, double *ul,
+               void *stream);
+
+/* DEVICE.  ug = Z^T ul: ug[g] = sum of ul[locals[k]], offsets[g] <= k < offsets[g+1]. */
+int fem_scatter(int64_t n_local, int64_t n_global, const int32_t *offsets, const int32_t *locals,
+                const double *ul, double *ug, void *stream);
+
+/* Device workspace bytes of fem_assembled_apply, fem_assembled_diagonal and
+ * fem_pcg_solve for this operator and map (two local and four global
+ * vectors, partial sums); 0 on invalid arguments. */
+size_t fem_assembled_workspace_bytes(const fem_cg_operator *op, const fem_assembly *as);
+
+/* DEVICE.  yg = Z^T (S + lambda M) Z ug, the FP64 operator of fem_cg_solve
+ * (op->G, op->wJ; the narrow fields of op are ignored) assembled over the
+ * shared nodes.  ug, yg: [n_global] FP64, not overlapping.  workspace: device,
+ * 256-byte aligned, at least fem_assembled_workspace_bytes(). */
+int fem_assembled_apply(const fem_cg_operator *op, const fem_assembly *as, const double *ug, double *yg,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/* DEVICE.  diag[n_global] = the diagonal of Z^T (S + lambda M) Z, i.e. Z^T of
+ * each element's diagonal (the Jacobi preconditioner of fem_pcg_solve). */
+int fem_assembled_diagonal(const fem_cg_operator *op, const fem_assembly *as, double *diag, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+/* DEVICE, blocking.  Preconditioned CG on the assembled system
+ * Z^T (S + lambda M) Z x = b, FP64 throughout (opt->mode must be 0; fusion is
+ * ignored), with the Jacobi preconditioner z = r / diag (diag as written by
+ * fem_assembled_diagonal; NULL: no preconditioner).  b, x: [n_global] FP64;
+ * x holds the initial guess on entry.  The solve stops when the FP64 true
+ * residual ||b - A x|| <= rtol ||b||; when the recursive residual meets the
+ * target first, the true residual is checked and, if it does not, the
+ * iteration restarts from it (rep->reliable_updates counts the checks,
+ * opt->history receives the true relative residuals).  Returns rep->status as
+ * fem_cg_solve does. */
+int fem_pcg_solve(const fem_cg_operator *op, const fem_assembly *as, const fem_cg_options *opt, const double *diag,
+                  const double *b, double *x, void *workspace, size_t workspace_bytes, fem_cg_report *rep,
+                  void *stream);
 
 /* ---------------------------------------------------------------------------
  * Ragged batches: independent applies of different meshes, degrees,

@@ -36,3 +36,31 @@ def cg(A, b: np.ndarray, x0: np.ndarray | None = None, rtol: float = 1e-10,
 def true_relative_residual(A, b: np.ndarray, x: np.ndarray) -> float:
     r = b - A(x)
     return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+def pcg(A, b: np.ndarray, Minv, x0: np.ndarray | None = None, rtol: float = 1e-10,
+        max_iters: int = 100000) -> tuple[np.ndarray, int, list[float]]:
+    """Preconditioned CG (the same recurrences with z = Minv(r) in place of r
+    in the direction and step length).  Stops on the unpreconditioned
+    recursive residual ||r|| <= rtol ||b||.  Return (x, iterations, ||r|| /
+    ||b|| per iteration)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - A(x) if x0 is not None else b.copy()
+    z = Minv(r)
+    p = z.copy()
+    rz = float(np.vdot(r, z))
+    bn = float(np.sqrt(np.vdot(b, b)))
+    hist = [float(np.sqrt(np.vdot(r, r))) / bn]
+    it = 0
+    while hist[-1] > rtol and it < max_iters:
+        Ap = A(p)
+        alpha = rz / float(np.vdot(p, Ap))
+        x += alpha * p
+        r -= alpha * Ap
+        z = Minv(r)
+        rz_new = float(np.vdot(r, z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        it += 1
+        hist.append(float(np.sqrt(np.vdot(r, r))) / bn)
+    return x, it, hist

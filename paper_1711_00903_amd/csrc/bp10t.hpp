@@ -300,7 +300,8 @@ hipError_t bp10t_launch_t(const ApplyArgs &a, hipStream_t s)
     const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
                                                                          : a.out_scale);
     // one workgroup per element; a grid cap splits the elements over launches
-    const int64_t chunk = a.grid_cap > 0 ? a.grid_cap : a.E;
+    int64_t chunk = a.grid_cap > 0 ? a.grid_cap : a.E;
+    if (chunk > max_grid(bp10t_threads(NQ))) chunk = max_grid(bp10t_threads(NQ));
     for (int64_t e0 = 0; e0 < a.E; e0 += chunk) {
         const unsigned grid = static_cast<unsigned>(a.E - e0 < chunk ? a.E - e0 : chunk);
         if constexpr (std::is_same<TV, double>::value) {

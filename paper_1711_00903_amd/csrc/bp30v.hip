@@ -298,8 +298,13 @@ static hipError_t bp30v_launch_t(int64_t E, const double *I1d, const double *Dgl
                                  const GlRule &rule, double lambda, const double *u, double *y, double beta,
                                  hipStream_t s)
 {
-    hipLaunchKernelGGL((bp30v_kernel<NQ, double, double>), dim3(static_cast<unsigned>(E)), dim3(bp30v_threads(NQ)),
-                       0, s, E, I1d, Dgl, X, rule, lambda, u, y, beta, 1.0, int64_t(0));
+    // one workgroup per element, split over launches of at most max_grid workgroups
+    const int64_t chunk = max_grid(bp30v_threads(NQ));
+    for (int64_t e0 = 0; e0 < E; e0 += chunk) {
+        const unsigned grid = static_cast<unsigned>(E - e0 < chunk ? E - e0 : chunk);
+        hipLaunchKernelGGL((bp30v_kernel<NQ, double, double>), dim3(grid), dim3(bp30v_threads(NQ)), 0, s, E, I1d,
+                           Dgl, X, rule, lambda, u, y, beta, 1.0, e0);
+    }
     return hipGetLastError();
 }
 

@@ -327,6 +327,7 @@ hipError_t bp35_launch_t(const ApplyArgs &a, hipStream_t s)
     const int64_t ngroups = (a.E + EPB - 1) / EPB;
     int64_t grid = ngroups;
     if (a.grid_cap > 0 && grid > a.grid_cap) grid = a.grid_cap;
+    if (grid > max_grid(threads_for(1, NQ, EPB))) grid = max_grid(threads_for(1, NQ, EPB));
     if (grid < 1) return hipSuccess;
     const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
                                                                          : a.out_scale);

@@ -212,7 +212,8 @@ static hipError_t bp35v_launch_t(int64_t E, const double *D1d, const double *X, 
                                  hipStream_t s)
 {
     // one workgroup per element; a grid cap splits the elements over launches
-    const int64_t chunk = grid_cap > 0 ? grid_cap : E;
+    int64_t chunk = grid_cap > 0 ? grid_cap : E;
+    if (chunk > max_grid(bp35v_threads(NQ))) chunk = max_grid(bp35v_threads(NQ));
     for (int64_t e0 = 0; e0 < E; e0 += chunk) {
         const unsigned grid = static_cast<unsigned>(E - e0 < chunk ? E - e0 : chunk);
         hipLaunchKernelGGL((bp35v_kernel<NQ>), dim3(grid), dim3(bp35v_threads(NQ)), 0, s, D1d, X, rule, lambda,

@@ -2,11 +2,15 @@
 // A = S(BP3.5) + lambda M(BP1.0) (Problem description section: the global
 // operator is block diagonal and symmetric positive definite for lambda > 0).
 //
-// One code path serves both arms:
+// One code path serves every arm:
 //   * FP64 CG: iterates, operator and vectors in FP64;
-//   * mixed precision: the Krylov iteration runs with FP32 vectors and an
-//     operator whose geometric data is stored in FP32, BF16 or FP16;
-// and both use reliable updates (residual replacement, Sleijpen & van der
+//   * mixed precision (mode 1): the Krylov iteration runs with an operator
+//     whose geometric data is stored in FP32, BF16 or FP16, and either FP64
+//     vectors and arithmetic (the *G64 storage modes) or FP32 vectors and
+//     arithmetic (FEM_F32, FEM_BF16G, FEM_F16G);
+//   * iterative refinement (mode 2): as mode 1, with the Krylov iteration
+//     restarted at every reliable update (an inner CG per refinement step);
+// and all use reliable updates (residual replacement, Sleijpen & van der
 // Vorst 1996; the mixed-precision form of Clark et al. 2010): the iterate is
 // accumulated in the iteration precision since the last update, and whenever
 // the recursive residual has dropped by `delta` relative to the last true
@@ -467,23 +471,31 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     // the recursion keeps falling), the next such check waits until the
     // recursive residual has halved again, so checks do not repeat every step.
     double check_at = target;
+    // mode 2 (iterative refinement): every reliable update also restarts the
+    // Krylov iteration from the replaced residual (p = r_lo, no direction
+    // update in the next step), so each refinement step is a fresh inner CG
+    // in the low precision, stopped when it has reduced the residual by delta
+    const bool restart_ir = opt->mode == 2;
+    bool fresh = true;   // p = r_lo already: no direction update in the next step
     int it = 0;
     while (!converged && it < opt->max_iters) {
         ++it;
+        const bool xpay = !fresh;
+        fresh = false;
         if (fused) {
-            // p <- r_lo + beta p (from the second iteration on), Ap, p . Ap
+            // p <- r_lo + beta p (except right after a (re)start), Ap, p . Ap
             if (apply_cgop(c, prec_lo, reinterpret_cast<const double *>(rl), reinterpret_cast<double *>(p),
-                           &sc->beta, it > 1, reinterpret_cast<double *>(Ap), partg) != hipSuccess)
+                           &sc->beta, xpay, reinterpret_cast<double *>(Ap), partg) != hipSuccess)
                 return FEM_ERR_HIP;
             fin(partg, cgop_groups(op->N, op->E), &sc->pAp, FIN_ALPHA);
         } else if (split) {
-            if (apply_A_split(c, prec_lo, it > 1 ? reinterpret_cast<const double *>(rl) : nullptr, &sc->beta,
+            if (apply_A_split(c, prec_lo, xpay ? reinterpret_cast<const double *>(rl) : nullptr, &sc->beta,
                               reinterpret_cast<double *>(p), reinterpret_cast<double *>(Ap), partg) != hipSuccess)
                 return FEM_ERR_HIP;
             hipLaunchKernelGGL(sum_kernel, G, B, 0, s, partg, op->E, part);
             fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
         } else {
-            if (it > 1) hipLaunchKernelGGL(xpay_kernel<TV>, G, B, 0, s, p, rl, n, sc);
+            if (xpay) hipLaunchKernelGGL(xpay_kernel<TV>, G, B, 0, s, p, rl, n, sc);
             if (apply_A(c, prec_lo, p, Ap) != hipSuccess) return FEM_ERR_HIP;
             hipLaunchKernelGGL((dot_kernel<TV, TV>), G, B, 0, s, p, Ap, n, part);
             fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
@@ -504,7 +516,8 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                 // reliable update: fold the low-precision iterate into x and
                 // replace the recursive residual by the true one
                 hipLaunchKernelGGL(merge_kernel<TV>, G, B, 0, s, x, xl, n);
-                if (true_residual(false) != hipSuccess) return FEM_ERR_HIP;
+                if (true_residual(restart_ir) != hipSuccess) return FEM_ERR_HIP;
+                fresh = restart_ir;
                 rep->reliable_updates += 1;
                 rep->hi_matvecs += 1;
                 if (!fetch()) return FEM_ERR_HIP;
@@ -519,8 +532,9 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
             }
         }
         // beta = rr_new / rr; rr = rr_new (the direction update itself is
-        // applied at the start of the next iteration)
-        fin(part2, kRedBlocks, &sc->rr_new, FIN_BETA);
+        // applied at the start of the next iteration; after a restart p and rr
+        // are already set)
+        if (!fresh) fin(part2, kRedBlocks, &sc->rr_new, FIN_BETA);
         if (hipGetLastError() != hipSuccess) return FEM_ERR_HIP;
     }
     if (!converged) {
@@ -554,6 +568,7 @@ size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt)
 int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,
              fem_cg_report *rep, hipStream_t s)
 {
+    // modes 1 and 2 differ only in the restart at a reliable update
     if (opt->mode == 0) return solve_t<double>(op, opt, FEM_F64, b, x, ws, rep, s);
     if (f64_fields(op->inner_prec)) return solve_t<double>(op, opt, op->inner_prec, b, x, ws, rep, s);
     return solve_t<float>(op, opt, op->inner_prec, b, x, ws, rep, s);

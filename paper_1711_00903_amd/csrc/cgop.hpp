@@ -303,8 +303,17 @@ inline int64_t cgop_groups(int N, int64_t E)
     constexpr int epb[kMaxN + 2] = {1, 1, cgop_epb(2), cgop_epb(3), cgop_epb(4), cgop_epb(5), cgop_epb(6),
                                     cgop_epb(7), cgop_epb(8), cgop_epb(9), cgop_epb(10), cgop_epb(11),
                                     cgop_epb(12), cgop_epb(13), cgop_epb(14), cgop_epb(15), cgop_epb(16)};
+    constexpr int threads[kMaxN + 2] = {64, 64, threads_for(0, 2, cgop_epb(2)), threads_for(0, 3, cgop_epb(3)),
+                                        threads_for(0, 4, cgop_epb(4)), threads_for(0, 5, cgop_epb(5)),
+                                        threads_for(0, 6, cgop_epb(6)), threads_for(0, 7, cgop_epb(7)),
+                                        threads_for(0, 8, cgop_epb(8)), threads_for(0, 9, cgop_epb(9)),
+                                        threads_for(0, 10, cgop_epb(10)), threads_for(0, 11, cgop_epb(11)),
+                                        threads_for(0, 12, cgop_epb(12)), threads_for(0, 13, cgop_epb(13)),
+                                        threads_for(0, 14, cgop_epb(14)), threads_for(0, 15, cgop_epb(15)),
+                                        threads_for(0, 16, cgop_epb(16))};
     const int e = epb[N + 1];
-    return (E + e - 1) / e;
+    const int64_t g = (E + e - 1) / e;
+    return g < max_grid(threads[N + 1]) ? g : max_grid(threads[N + 1]);
 }
 
 template <int NQ, class TG>
@@ -312,7 +321,10 @@ hipError_t cgop_launch_nq(const CgopArgs &a, hipStream_t s)
 {
     static_assert(cgop_fits(NQ), "one-pass CG operator exceeds the LDS of a workgroup");
     constexpr int EPB = cgop_epb(NQ);
-    const int64_t grid = (a.E + EPB - 1) / EPB;
+    // the kernel loops over element groups beyond the grid; the partial count
+    // (cgop_groups) is the grid
+    int64_t grid = (a.E + EPB - 1) / EPB;
+    if (grid > max_grid(threads_for(0, NQ, EPB))) grid = max_grid(threads_for(0, NQ, EPB));
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL((cgop_kernel<NQ, EPB, TG>), dim3(static_cast<unsigned>(grid)),
                        dim3(threads_for(0, NQ, EPB)), 0, s, a.E, a.I1d, a.D1d,

@@ -151,6 +151,16 @@ size_t cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *opt);
 int cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x, void *ws,
              fem_cg_report *rep, hipStream_t s);
 
+size_t assembled_workspace_bytes(const fem_cg_operator *op, const fem_assembly *as);
+int assembled_apply(const fem_cg_operator *op, const fem_assembly *as, const double *ug, double *yg, void *ws,
+                    hipStream_t s);
+int assembled_diagonal(const fem_cg_operator *op, const fem_assembly *as, double *diag, void *ws, hipStream_t s);
+int pcg_solve(const fem_cg_operator *op, const fem_assembly *as, const fem_cg_options *opt, const double *diag,
+              const double *b, double *x, void *ws, fem_cg_report *rep, hipStream_t s);
+hipError_t launch_gather(const int32_t *gid, const double *ug, double *ul, int64_t nl, int64_t ng, hipStream_t s);
+hipError_t launch_scatter(const int32_t *off, const int32_t *loc, const double *ul, double *ug, int64_t ng,
+                          int64_t nl, const double *pdot, double *part, hipStream_t s);
+
 int check_desc(const fem_apply_desc &d);
 int enqueue_desc(const fem_apply_desc &d, hipStream_t s);
 double desc_bytes(const fem_apply_desc &d);
@@ -189,6 +199,14 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 {
     const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
     return pa < pb + nb && pb < pa + na;
+}
+
+// FP64 fields u and y of E elements of degree N share bytes: a workgroup
+// could then overwrite another element's input before that element read it.
+bool fields_overlap(int N, int64_t E, const void *u, const void *y)
+{
+    const size_t bytes = static_cast<size_t>(E) * (N + 1) * (N + 1) * (N + 1) * sizeof(double);
+    return overlap(u, bytes, y, bytes);
 }
 
 int common_checks(int op, int N, int64_t E, int prec, float geo_scale, const void *u, const void *y)
@@ -310,6 +328,11 @@ const char *fem_status_str(int status)
 }
 
 int fem_version(void) { return 100; }
+
+#ifndef FEM_BUILD_ID
+#define FEM_BUILD_ID "unknown"
+#endif
+const char *fem_build_id(void) { return FEM_BUILD_ID; }
 int fem_max_degree(void) { return kMaxN; }
 int64_t fem_max_elements(void) { return kMaxElements; }
 
@@ -379,8 +402,9 @@ int fem_stiff_collocated_vertex_apply(int N, int64_t E, const double *D1d, const
 {
     if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
     if (E == 0) return FEM_OK;
-    if (!D1d || !X || !u || !y || static_cast<const void *>(u) == static_cast<const void *>(y)) return FEM_ERR_ARG;
+    if (!D1d || !X || !u || !y) return FEM_ERR_ARG;
     if (!aligned16(D1d) || !aligned16(X) || !aligned16(u) || !aligned16(y)) return FEM_ERR_ALIGN;
+    if (fields_overlap(N, E, u, y)) return FEM_ERR_ARG;
     return finish(launch_bp35v(N, E, D1d, X, lambda, u, y, beta, 0, static_cast<hipStream_t>(stream)));
 }
 
@@ -389,9 +413,9 @@ int fem_stiff_dealiased_vertex_apply(int N, int64_t E, const double *I1d, const 
 {
     if (N < 1 || N > kMaxN || E < 0 || E > kMaxElements) return FEM_ERR_ARG;
     if (E == 0) return FEM_OK;
-    if (!I1d || !Dgl || !X || !u || !y || static_cast<const void *>(u) == static_cast<const void *>(y))
-        return FEM_ERR_ARG;
+    if (!I1d || !Dgl || !X || !u || !y) return FEM_ERR_ARG;
     if (!aligned16(I1d) || !aligned16(Dgl) || !aligned16(X) || !aligned16(u) || !aligned16(y)) return FEM_ERR_ALIGN;
+    if (fields_overlap(N, E, u, y)) return FEM_ERR_ARG;
     return finish(launch_bp30v(N, E, I1d, Dgl, X, lambda, u, y, beta, static_cast<hipStream_t>(stream)));
 }
 
@@ -452,11 +476,19 @@ int fem_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
     return finish(launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
 }
 
+int fem_lds_bandwidth(int mode, int64_t workgroups, int iters, double *sink, void *stream)
+{
+    if (mode < 0 || mode > 3 || workgroups < 1 || workgroups > max_grid(256) || iters < 1) return FEM_ERR_ARG;
+    if (!sink) return FEM_ERR_ARG;
+    if (!aligned16(sink)) return FEM_ERR_ALIGN;
+    return finish(launch_lds_probe(mode, workgroups, iters, sink, static_cast<hipStream_t>(stream)));
+}
+
 static int cg_check(const fem_cg_operator *op, const fem_cg_options *opt)
 {
     if (!op || !opt) return FEM_ERR_ARG;
     if (op->N < 1 || op->N > kMaxN || op->E < 0 || op->E > kMaxElements) return FEM_ERR_ARG;
-    if (opt->mode != 0 && opt->mode != 1) return FEM_ERR_ARG;
+    if (opt->mode < 0 || opt->mode > 2) return FEM_ERR_ARG;
     if (opt->fusion < FEM_CG_FUSE_AUTO || opt->fusion > FEM_CG_FUSE_ONEPASS) return FEM_ERR_ARG;
     if (!(opt->rtol > 0.0) || opt->max_iters < 0 || opt->delta < 0.0 || opt->delta >= 1.0 ||
         opt->check_every < 0 || opt->history_len < 0 || (opt->history_len > 0 && !opt->history))
@@ -466,7 +498,7 @@ static int cg_check(const fem_cg_operator *op, const fem_cg_options *opt)
     if (!op->I1d || !op->D1d || !op->G || (op->lambda != 0.0 && !op->wJ)) return FEM_ERR_ARG;
     if (!aligned16(op->G) || (op->wJ && !aligned16(op->wJ)) || !aligned16(op->I1d) || !aligned16(op->D1d))
         return FEM_ERR_ALIGN;
-    if (opt->mode == 1) {
+    if (opt->mode != 0) {
         const int p = op->inner_prec;
         if (p != FEM_F32 && p != FEM_BF16G && p != FEM_F16G && p != FEM_F32G64 && p != FEM_BF16G64 &&
             p != FEM_F16G64)
@@ -499,6 +531,121 @@ int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const dou
     if (overlap(b, n * 8, x, n * 8)) return FEM_ERR_ARG;
     if (workspace_bytes < cg_workspace_bytes(op, opt)) return FEM_ERR_WORKSPACE;
     return cg_solve(op, opt, b, x, workspace, rep, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------- assembled operator
+
+static bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+static constexpr int64_t kMaxIndex = 2147483647LL;   // int32 node numbers
+
+int fem_assembly_inverse_map(int64_t n_local, const int32_t *gather, int64_t n_global, int32_t *offsets,
+                             int32_t *locals)
+{
+    if (n_local < 0 || n_local > kMaxIndex || n_global < 1 || n_global > kMaxIndex) return FEM_ERR_ARG;
+    if (!offsets || (n_local > 0 && (!gather || !locals))) return FEM_ERR_ARG;
+    for (int64_t l = 0; l < n_local; ++l)
+        if (gather[l] < 0 || gather[l] >= n_global) return FEM_ERR_ARG;
+    // counting sort by global node, stable: each node's copies stay ascending
+    std::memset(offsets, 0, static_cast<size_t>(n_global + 1) * sizeof(int32_t));
+    for (int64_t l = 0; l < n_local; ++l) offsets[gather[l] + 1] += 1;
+    for (int64_t g = 0; g < n_global; ++g) offsets[g + 1] += offsets[g];
+    std::vector<int32_t> next(offsets, offsets + n_global);
+    for (int64_t l = 0; l < n_local; ++l) locals[next[gather[l]]++] = static_cast<int32_t>(l);
+    return FEM_OK;
+}
+
+int fem_gather(int64_t n_local, int64_t n_global, const int32_t *gather, const double *ug, double *ul,
+               void *stream)
+{
+    if (n_local < 0 || n_local > kMaxIndex || n_global < 0 || n_global > kMaxIndex) return FEM_ERR_ARG;
+    if (n_local == 0) return FEM_OK;
+    if (!gather || !ug || !ul) return FEM_ERR_ARG;
+    if (!aligned4(gather) || !aligned16(ug) || !aligned16(ul)) return FEM_ERR_ALIGN;
+    if (overlap(ug, n_global * 8, ul, n_local * 8)) return FEM_ERR_ARG;
+    return finish(launch_gather(gather, ug, ul, n_local, n_global, static_cast<hipStream_t>(stream)));
+}
+
+int fem_scatter(int64_t n_local, int64_t n_global, const int32_t *offsets, const int32_t *locals,
+                const double *ul, double *ug, void *stream)
+{
+    if (n_local < 0 || n_local > kMaxIndex || n_global < 0 || n_global > kMaxIndex) return FEM_ERR_ARG;
+    if (n_global == 0) return FEM_OK;
+    if (!offsets || !locals || !ul || !ug) return FEM_ERR_ARG;
+    if (!aligned4(offsets) || !aligned4(locals) || !aligned16(ug) || !aligned16(ul)) return FEM_ERR_ALIGN;
+    if (overlap(ug, n_global * 8, ul, n_local * 8)) return FEM_ERR_ARG;
+    return finish(launch_scatter(offsets, locals, ul, ug, n_global, n_local, nullptr, nullptr,
+                                 static_cast<hipStream_t>(stream)));
+}
+
+// Operator (FP64 data only) and map of the assembled calls.
+static int assembled_check(const fem_cg_operator *op, const fem_assembly *as)
+{
+    if (!op || !as) return FEM_ERR_ARG;
+    if (op->N < 1 || op->N > kMaxN || op->E < 1 || op->lambda < 0.0) return FEM_ERR_ARG;
+    const int64_t nl = op->E * static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
+    if (nl > kMaxIndex || as->n_global < 1 || as->n_global > nl) return FEM_ERR_ARG;
+    if (!op->I1d || !op->D1d || !op->G || (op->lambda != 0.0 && !op->wJ)) return FEM_ERR_ARG;
+    if (!as->gather || !as->offsets || !as->locals) return FEM_ERR_ARG;
+    if (!aligned16(op->G) || (op->wJ && !aligned16(op->wJ)) || !aligned16(op->I1d) || !aligned16(op->D1d))
+        return FEM_ERR_ALIGN;
+    if (!aligned4(as->gather) || !aligned4(as->offsets) || !aligned4(as->locals)) return FEM_ERR_ALIGN;
+    return FEM_OK;
+}
+
+size_t fem_assembled_workspace_bytes(const fem_cg_operator *op, const fem_assembly *as)
+{
+    if (assembled_check(op, as) != FEM_OK) return 0;
+    return assembled_workspace_bytes(op, as);
+}
+
+static int assembled_ws_check(const fem_cg_operator *op, const fem_assembly *as, void *ws, size_t ws_bytes)
+{
+    if (!ws) return FEM_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return FEM_ERR_ALIGN;
+    return ws_bytes < assembled_workspace_bytes(op, as) ? FEM_ERR_WORKSPACE : FEM_OK;
+}
+
+int fem_assembled_apply(const fem_cg_operator *op, const fem_assembly *as, const double *ug, double *yg,
+                        void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = assembled_check(op, as);
+    if (st != FEM_OK) return st;
+    if (!ug || !yg) return FEM_ERR_ARG;
+    if (!aligned16(ug) || !aligned16(yg)) return FEM_ERR_ALIGN;
+    if (overlap(ug, as->n_global * 8, yg, as->n_global * 8)) return FEM_ERR_ARG;
+    if ((st = assembled_ws_check(op, as, workspace, workspace_bytes)) != FEM_OK) return st;
+    return assembled_apply(op, as, ug, yg, workspace, static_cast<hipStream_t>(stream));
+}
+
+int fem_assembled_diagonal(const fem_cg_operator *op, const fem_assembly *as, double *diag, void *workspace,
+                           size_t workspace_bytes, void *stream)
+{
+    int st = assembled_check(op, as);
+    if (st != FEM_OK) return st;
+    if (!diag) return FEM_ERR_ARG;
+    if (!aligned16(diag)) return FEM_ERR_ALIGN;
+    if ((st = assembled_ws_check(op, as, workspace, workspace_bytes)) != FEM_OK) return st;
+    return assembled_diagonal(op, as, diag, workspace, static_cast<hipStream_t>(stream));
+}
+
+int fem_pcg_solve(const fem_cg_operator *op, const fem_assembly *as, const fem_cg_options *opt, const double *diag,
+                  const double *b, double *x, void *workspace, size_t workspace_bytes, fem_cg_report *rep,
+                  void *stream)
+{
+    int st = assembled_check(op, as);
+    if (st != FEM_OK) return st;
+    if (!opt || !rep || opt->mode != 0) return FEM_ERR_ARG;
+    if (!(opt->rtol > 0.0) || opt->max_iters < 0 || opt->check_every < 0 || opt->history_len < 0 ||
+        (opt->history_len > 0 && !opt->history))
+        return FEM_ERR_ARG;
+    *rep = fem_cg_report{};
+    if (!b || !x) return FEM_ERR_ARG;
+    if (!aligned16(b) || !aligned16(x) || (diag && !aligned16(diag))) return FEM_ERR_ALIGN;
+    if (overlap(b, as->n_global * 8, x, as->n_global * 8) ||
+        (diag && overlap(diag, as->n_global * 8, x, as->n_global * 8)))
+        return FEM_ERR_ARG;
+    if ((st = assembled_ws_check(op, as, workspace, workspace_bytes)) != FEM_OK) return st;
+    return pcg_solve(op, as, opt, diag, b, x, workspace, rep, static_cast<hipStream_t>(stream));
 }
 
 int fem_tune_set(int op, int N, int prec, int epb, int grid_cap)

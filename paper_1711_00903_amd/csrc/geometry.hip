@@ -205,10 +205,73 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
     const int64_t n = static_cast<int64_t>(bytes / 16);
     if (n == 0) return hipSuccess;
     const int64_t per = kCopyThreads * kCopyUnroll;
-    const int64_t blocks = (n + per - 1) / per;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kCopyThreads), 0, s,
-                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n);
+    // launches of at most max_grid workgroups, each over its own piece
+    const int64_t piece = max_grid(kCopyThreads) * per;
+    for (int64_t v0 = 0; v0 < n; v0 += piece) {
+        const int64_t m = n - v0 < piece ? n - v0 : piece;
+        hipLaunchKernelGGL(copy_kernel, dim3(static_cast<unsigned>((m + per - 1) / per)), dim3(kCopyThreads), 0, s,
+                           static_cast<const u32x4 *>(src) + v0, static_cast<u32x4 *>(dst) + v0, m);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LDS bandwidth probe: the shared-memory term of the empirical performance
+// model (Empirical performance model section, eq. sharedRoof), measured
+// rather than taken from a data sheet.  Each workgroup of kLdsThreads lanes
+// owns a 32 KiB LDS buffer; every lane reads (or writes) `iters` x kLdsUnroll
+// distinct vectors of `W` doubles, lane-consecutive (a wave touches a
+// contiguous 64 W x 8-byte span: no bank conflicts), so the LDS moves
+// workgroups x kLdsThreads x iters x kLdsUnroll x 8 W bytes.  The result is
+// summed into sink[] so that no access is dead.
+// ---------------------------------------------------------------------------
+constexpr int kLdsThreads = 256;
+constexpr int kLdsUnroll = 16;
+constexpr int kLdsValues = 4096;   // doubles per workgroup buffer (32 KiB)
+
+template <int W, bool WRITE>
+__global__ __launch_bounds__(kLdsThreads) void lds_probe_kernel(int iters, double *__restrict__ sink)
+{
+    typedef double vec __attribute__((ext_vector_type(W)));
+    __shared__ __align__(16) double buf[kLdsValues];
+    const int t = threadIdx.x;
+    for (int q = t; q < kLdsValues; q += kLdsThreads) buf[q] = static_cast<double>(q);
+    __syncthreads();
+    vec *v = reinterpret_cast<vec *>(buf);
+    constexpr int nvec = kLdsValues / W;
+    constexpr int stride = nvec / kLdsUnroll;   // a lane's kLdsUnroll accesses of one pass are distinct
+    vec acc = vec(0.0);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < kLdsUnroll; ++u) {
+            const int idx = (t + stride * u + it * 7) & (nvec - 1);
+            if (WRITE) {
+                v[idx] = acc + static_cast<double>(u);
+                __asm__ volatile("" ::: "memory");   // keep every store (no merging across the loop)
+            } else {
+                acc += v[idx];
+            }
+        }
+        if (WRITE) acc += 1.0;
+    }
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += acc[w];
+    if (WRITE) s += buf[t];
+    sink[static_cast<int64_t>(blockIdx.x) * kLdsThreads + t] = s;
+}
+
+hipError_t launch_lds_probe(int mode, int64_t workgroups, int iters, double *sink, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(workgroups)), block(kLdsThreads);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL((lds_probe_kernel<1, false>), grid, block, 0, s, iters, sink); break;
+    case 1: hipLaunchKernelGGL((lds_probe_kernel<2, false>), grid, block, 0, s, iters, sink); break;
+    case 2: hipLaunchKernelGGL((lds_probe_kernel<1, true>), grid, block, 0, s, iters, sink); break;
+    case 3: hipLaunchKernelGGL((lds_probe_kernel<2, true>), grid, block, 0, s, iters, sink); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

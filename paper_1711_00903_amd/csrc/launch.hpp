@@ -19,6 +19,17 @@ enum Op { OP_BP10 = 0, OP_BP35 = 1, OP_BP30 = 2 };
 constexpr int kMaxN = 15;
 constexpr int kMaxEpbChoices = 4;
 
+// A dispatch counts its work-items in 32 bits (grid x workgroup size < 2^32)
+// and its workgroups below 2^31.  Largest number of `threads`-thread
+// workgroups one launch may have; element kernels with more element groups
+// than that loop over them (persistent form) or split the elements over
+// several launches.
+constexpr int64_t max_grid(int threads)
+{
+    const int64_t g = 0xFFFFFFFFLL / threads;
+    return g < 0x7FFFFFFFLL ? g : 0x7FFFFFFFLL;
+}
+
 struct ApplyArgs {
     int op;
     int N;
@@ -67,6 +78,7 @@ hipError_t launch_geometry(int N, int64_t E, int quad, const double *X, void *G,
 hipError_t launch_node_coords(int N, int64_t E, int quad, const double *X, double *xyz,
                               hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+hipError_t launch_lds_probe(int mode, int64_t workgroups, int iters, double *sink, hipStream_t s);
 
 // Host-side quadrature and tables (basis.cpp).
 int basis_tables(int N, double *r_gll, double *w_gll, double *r_gl, double *w_gl, double *I1d,

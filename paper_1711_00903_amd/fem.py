@@ -74,6 +74,10 @@ class CgReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Assembly(C.Structure):
+    _fields_ = [("n_global", C.c_int64), ("gather", C.c_void_p), ("offsets", C.c_void_p), ("locals", C.c_void_p)]
+
+
 class ApplyDesc(C.Structure):
     _fields_ = [("op", C.c_int), ("N", C.c_int), ("E", C.c_int64), ("prec", C.c_int),
                 ("I1d", C.c_void_p), ("D1d", C.c_void_p), ("Dgl", C.c_void_p), ("G", C.c_void_p),
@@ -84,6 +88,7 @@ class ApplyDesc(C.Structure):
 _SIGS = {
     "fem_status_str": ([C.c_int], C.c_char_p),
     "fem_version": ([], C.c_int),
+    "fem_build_id": ([], C.c_char_p),
     "fem_max_degree": ([], C.c_int),
     "fem_max_elements": ([], _i64),
     "fem_basis_tables": ([C.c_int] + [_dp] * 7, C.c_int),
@@ -102,9 +107,18 @@ _SIGS = {
     "fem_stiff_dealiased_apply": ([C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp,
                                    C.c_double, C.c_int, C.c_float, _vp], C.c_int),
     "fem_stream_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
+    "fem_lds_bandwidth": ([C.c_int, _i64, C.c_int, _vp, _vp], C.c_int),
     "fem_cg_workspace_bytes": ([C.POINTER(CgOperator), C.POINTER(CgOptions)], C.c_size_t),
     "fem_cg_solve": ([C.POINTER(CgOperator), C.POINTER(CgOptions), _vp, _vp, _vp, C.c_size_t,
                       C.POINTER(CgReport), _vp], C.c_int),
+    "fem_assembly_inverse_map": ([_i64, _vp, _i64, _vp, _vp], C.c_int),
+    "fem_gather": ([_i64, _i64, _vp, _vp, _vp, _vp], C.c_int),
+    "fem_scatter": ([_i64, _i64, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "fem_assembled_workspace_bytes": ([C.POINTER(CgOperator), C.POINTER(Assembly)], C.c_size_t),
+    "fem_assembled_apply": ([C.POINTER(CgOperator), C.POINTER(Assembly), _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "fem_assembled_diagonal": ([C.POINTER(CgOperator), C.POINTER(Assembly), _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "fem_pcg_solve": ([C.POINTER(CgOperator), C.POINTER(Assembly), C.POINTER(CgOptions), _vp, _vp, _vp, _vp,
+                       C.c_size_t, C.POINTER(CgReport), _vp], C.c_int),
     "fem_batch_apply": ([C.POINTER(ApplyDesc), C.c_int, _vp], C.c_int),
     "fem_batch_graph_create": ([C.POINTER(ApplyDesc), C.c_int, C.c_int, _vp, C.POINTER(C.c_void_p)], C.c_int),
     "fem_batch_graph_launch": ([_vp, _vp], C.c_int),
@@ -165,6 +179,10 @@ def _stream(s):
 
 def fem_version() -> int:
     return lib().fem_version()
+
+
+def fem_build_id() -> str:
+    return lib().fem_build_id().decode()
 
 
 def fem_max_degree() -> int:
@@ -264,6 +282,10 @@ def fem_stream_copy(src, dst, nbytes: int, stream=None) -> None:
     _check(lib().fem_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "fem_stream_copy")
 
 
+def fem_lds_bandwidth(mode: int, workgroups: int, iters: int, sink, stream=None) -> None:
+    _check(lib().fem_lds_bandwidth(mode, workgroups, iters, _ptr(sink), _stream(stream)), "fem_lds_bandwidth")
+
+
 def fem_cg_workspace_bytes(op: CgOperator, opt: CgOptions) -> int:
     return int(lib().fem_cg_workspace_bytes(C.byref(op), C.byref(opt)))
 
@@ -278,6 +300,55 @@ def fem_cg_solve(op: CgOperator, opt: CgOptions, b, x, workspace, workspace_byte
                             workspace_bytes, C.byref(rep), _stream(stream))
     if raise_on_error and st not in (FEM_OK, FEM_ERR_NOT_CONVERGED, FEM_ERR_BREAKDOWN):
         raise FemError(st, "fem_cg_solve")
+    return rep
+
+
+def fem_assembly_inverse_map(gather: np.ndarray, n_global: int) -> tuple[np.ndarray, np.ndarray]:
+    """(offsets [n_global + 1], locals [n_local]) int32 host arrays of a host
+    int32 gather map."""
+    g = np.ascontiguousarray(gather, dtype=np.int32).ravel()
+    off = np.zeros(n_global + 1, dtype=np.int32)
+    loc = np.zeros(g.size, dtype=np.int32)
+    _check(lib().fem_assembly_inverse_map(g.size, g.ctypes.data, n_global, off.ctypes.data, loc.ctypes.data),
+           "fem_assembly_inverse_map")
+    return off, loc
+
+
+def fem_gather(n_local, n_global, gather, ug, ul, stream=None) -> None:
+    _check(lib().fem_gather(n_local, n_global, _ptr(gather), _ptr(ug), _ptr(ul), _stream(stream)), "fem_gather")
+
+
+def fem_scatter(n_local, n_global, offsets, locals_, ul, ug, stream=None) -> None:
+    _check(lib().fem_scatter(n_local, n_global, _ptr(offsets), _ptr(locals_), _ptr(ul), _ptr(ug), _stream(stream)),
+           "fem_scatter")
+
+
+def fem_assembled_workspace_bytes(op: CgOperator, asm: Assembly) -> int:
+    return int(lib().fem_assembled_workspace_bytes(C.byref(op), C.byref(asm)))
+
+
+def fem_assembled_apply(op: CgOperator, asm: Assembly, ug, yg, workspace, workspace_bytes: int,
+                        stream=None) -> None:
+    _check(lib().fem_assembled_apply(C.byref(op), C.byref(asm), _ptr(ug), _ptr(yg), _ptr(workspace),
+                                     workspace_bytes, _stream(stream)), "fem_assembled_apply")
+
+
+def fem_assembled_diagonal(op: CgOperator, asm: Assembly, diag, workspace, workspace_bytes: int,
+                           stream=None) -> None:
+    _check(lib().fem_assembled_diagonal(C.byref(op), C.byref(asm), _ptr(diag), _ptr(workspace), workspace_bytes,
+                                        _stream(stream)), "fem_assembled_diagonal")
+
+
+def fem_pcg_solve(op: CgOperator, asm: Assembly, opt: CgOptions, diag, b, x, workspace, workspace_bytes: int,
+                  stream=None, raise_on_error: bool = True) -> CgReport:
+    """Blocking Jacobi-PCG solve on the assembled operator; returns the report
+    (FEM_ERR_NOT_CONVERGED / FEM_ERR_BREAKDOWN in the report, as for
+    fem_cg_solve)."""
+    rep = CgReport()
+    st = lib().fem_pcg_solve(C.byref(op), C.byref(asm), C.byref(opt), _ptr(diag), _ptr(b), _ptr(x),
+                             _ptr(workspace), workspace_bytes, C.byref(rep), _stream(stream))
+    if raise_on_error and st not in (FEM_OK, FEM_ERR_NOT_CONVERGED, FEM_ERR_BREAKDOWN):
+        raise FemError(st, "fem_pcg_solve")
     return rep
 
 

@@ -149,17 +149,17 @@ class DeviceMesh:
         return y
 
     # ---------------------------------------------------------------- CG
-    def cg_solve(self, b, x, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
-                 rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
-                 check_every: int = 1, fusion: int = fem.FEM_CG_FUSE_AUTO, history: int = 0,
-                 stream=None) -> dict:
-        """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors."""
+    def cg_structs(self, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
+                   rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
+                   check_every: int = 1, fusion: int = fem.FEM_CG_FUSE_AUTO, history: int = 0):
+        """(fem_cg_operator, fem_cg_options, history buffer) of a solve of
+        (S + lam M) x = b on this mesh, with the geometric data it needs built."""
         G64, _ = self.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
         _, wJ64 = self.geometry(fem.FEM_QUAD_GL, fem.FEM_F64, want_G=False, kind="wJ")
         op = fem.CgOperator(N=self.N, E=self.E, I1d=self.I1d.data_ptr(), D1d=self.D1d.data_ptr(),
                             G=G64.data_ptr(), wJ=wJ64.data_ptr() if lam else None, lam=lam,
                             inner_prec=inner_prec)
-        if mode == 1:
+        if mode != 0:
             Glo, _ = self.geometry(fem.FEM_QUAD_GLL, inner_prec, want_wJ=False)
             _, wJlo = self.geometry(fem.FEM_QUAD_GL, inner_prec, want_G=False, kind="wJ")
             op.G_lo = Glo.data_ptr()
@@ -171,9 +171,68 @@ class DeviceMesh:
                             check_every=check_every, fusion=int(fusion),
                             history=ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history else None,
                             history_len=history)
+        return op, opt, hist
+
+    def cg_solve(self, b, x, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
+                 rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
+                 check_every: int = 1, fusion: int = fem.FEM_CG_FUSE_AUTO, history: int = 0,
+                 stream=None) -> dict:
+        """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors."""
+        op, opt, hist = self.cg_structs(lam, mode, inner_prec, rtol, max_iters, delta, check_every, fusion,
+                                        history)
         nbytes = fem.fem_cg_workspace_bytes(op, opt)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         rep = fem.fem_cg_solve(op, opt, b, x, ws, nbytes, stream)
+        del ws
+        out = rep.as_dict()
+        if history:
+            out["history"] = list(hist[:rep.history_count])
+        return out
+
+    # ---------------------------------------------------------------- assembled operator
+    def set_assembly(self, gather: np.ndarray, n_global: int) -> None:
+        """The global numbering of this mesh's nodes (gather [E, Np] int32 host
+        array): the device gather map and its inverse (fem_assembly_inverse_map)."""
+        off, loc = fem.fem_assembly_inverse_map(gather, n_global)
+        self.n_global = int(n_global)
+        self._gather = torch.from_numpy(np.ascontiguousarray(gather, dtype=np.int32)).to(self.device)
+        self._offsets = torch.from_numpy(off).to(self.device)
+        self._locals = torch.from_numpy(loc).to(self.device)
+        self.asm = fem.Assembly(n_global=self.n_global, gather=self._gather.data_ptr(),
+                                offsets=self._offsets.data_ptr(), locals=self._locals.data_ptr())
+
+    def _assembled_ws(self, op):
+        nbytes = fem.fem_assembled_workspace_bytes(op, self.asm)
+        if nbytes == 0:
+            raise fem.FemError(fem.FEM_ERR_ARG, "fem_assembled_workspace_bytes")
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device), nbytes
+
+    def assembled_apply(self, ug, lam: float = 1.0, yg=None, stream=None):
+        """yg = Z^T (S + lam M) Z ug on the global nodes (FP64)."""
+        op, _, _ = self.cg_structs(lam)
+        yg = torch.empty(self.n_global, dtype=torch.float64, device=self.device) if yg is None else yg
+        ws, nbytes = self._assembled_ws(op)
+        fem.fem_assembled_apply(op, self.asm, ug, yg, ws, nbytes, stream)
+        return yg
+
+    def assembled_diagonal(self, lam: float = 1.0, stream=None):
+        op, _, _ = self.cg_structs(lam)
+        d = torch.empty(self.n_global, dtype=torch.float64, device=self.device)
+        ws, nbytes = self._assembled_ws(op)
+        fem.fem_assembled_diagonal(op, self.asm, d, ws, nbytes, stream)
+        return d
+
+    def pcg_solve(self, b, x, lam: float = 1.0, jacobi: bool = True, rtol: float = 1e-10,
+                  max_iters: int = 20000, check_every: int = 1, history: int = 0, stream=None) -> dict:
+        """Jacobi-PCG (or plain CG with jacobi=False) on the assembled system;
+        b, x FP64 [n_global] device tensors."""
+        op, opt, hist = self.cg_structs(lam, 0, 0, rtol, max_iters, 0.1, check_every, 0, history)
+        ws, nbytes = self._assembled_ws(op)
+        diag = None
+        if jacobi:
+            diag = torch.empty(self.n_global, dtype=torch.float64, device=self.device)
+            fem.fem_assembled_diagonal(op, self.asm, diag, ws, nbytes, stream)
+        rep = fem.fem_pcg_solve(op, self.asm, opt, diag, b, x, ws, nbytes, stream)
         del ws
         out = rep.as_dict()
         if history:

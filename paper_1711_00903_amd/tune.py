@@ -41,6 +41,71 @@ def alg_flops(op: str, N: int, E: int) -> int:
     return E * f
 
 
+_F64_FIELDS = (fem.FEM_F64, fem.FEM_F32G64, fem.FEM_BF16G64, fem.FEM_F16G64)
+
+
+def kernel_family(op: str, N: int, epb: int) -> str:
+    """The kernel an apply runs with `epb` elements per workgroup (the
+    library's dispatch): line-per-lane kernels with one element per
+    workgroup (BP1.0, BP3.0 at every degree, BP3.5 from Nq = 11), the column
+    kernels otherwise."""
+    if op == "BP10":
+        return "bp10t" if epb == 1 else "bp10"
+    if op == "BP35":
+        return "bp35t" if epb == 1 and N + 1 >= 11 else "bp35"
+    return "bp30t" if epb == 1 else "bp30"
+
+
+def lds_values(family: str, N: int) -> tuple[int, int]:
+    """(values read, values written) in LDS per element by each kernel's
+    schedule (s_r, s_w of the Empirical performance model section, eq.
+    sharedRoof, in values of the compute type; q = Nq, g = Ng).  Uniform
+    table reads (the same address on every lane) are not counted.
+
+    * bp35 (lane per GLL column): u staged (q^3 writes); each point's r- and
+      s-derivative read a row and a column (2 q^4), wr and ws staged (2 q^3),
+      the transposes read a row and a column per point again (2 q^4).
+    * bp35t (lane per line): u in, r-derivative out, s-derivative in place,
+      metric step on QR and QS, two transposes in place, the final column
+      sum: 8 q^3 reads, 7 q^3 writes.
+    * bp10t (lane per line): every direction turned once through LDS (t- and
+      s-interpolation, r-direction in place, s- and t-projection) plus the
+      staged scaled Jacobians: 2 g q^2 + 2 g^2 q + g^3 reads and writes each.
+    * bp10 (lane per output): r- and s-interpolation and s- and r-projection
+      each read a whole line per output: 2 g q^3 + 2 g^2 q^2 reads;
+      q^3 + 2 g q^2 + g^2 q writes.
+    * bp30t (lane per line): the BP1.0 turns at both ends, the r-, s- and
+      t-work on the Gauss grid (two derivatives out, metric step, two
+      transposes, the r-transpose reading three volumes): 2 g q^2 + 2 g^2 q
+      + 9 g^3 reads, 2 g q^2 + 2 g^2 q + 7 g^3 writes.
+    * bp30 (lane per Gauss column): whole-line reads per output in the r- and
+      s-interpolation and projection (2 g q^3 + 2 g^2 q^2) and in the
+      gradient and its transpose (4 g^4); q^3 + 2 g q^2 + g^2 q + 3 g^3 writes.
+    """
+    q, g = N + 1, N + 2
+    if family == "bp35":
+        return 4 * q ** 4, 3 * q ** 3
+    if family == "bp35t":
+        return 8 * q ** 3, 7 * q ** 3
+    if family == "bp10t":
+        v = 2 * g * q * q + 2 * g * g * q + g ** 3
+        return v, v
+    if family == "bp10":
+        return 2 * g * q ** 3 + 2 * g * g * q * q, q ** 3 + 2 * g * q * q + g * g * q
+    if family == "bp30t":
+        return 2 * g * q * q + 2 * g * g * q + 9 * g ** 3, 2 * g * q * q + 2 * g * g * q + 7 * g ** 3
+    if family == "bp30":
+        return 2 * g * q ** 3 + 2 * g * g * q * q + 4 * g ** 4, q ** 3 + 2 * g * q * q + g * g * q + 3 * g ** 3
+    raise ValueError(family)
+
+
+def lds_bytes(op: str, N: int, E: int, prec: int, epb: int) -> int:
+    """LDS bytes (read + written) of one apply: values of the compute type
+    (FP64 with FP64 fields, FP32 otherwise)."""
+    r, w = lds_values(kernel_family(op, N, epb), N)
+    return E * (r + w) * (8 if prec in _F64_FIELDS else 4)
+
+
 def _time(fn, reps: int, stream) -> float:
     for _ in range(2):
         fn()

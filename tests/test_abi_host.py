@@ -214,3 +214,104 @@ def test_batch_validation_on_host(fem):
     assert ei.value.status == fem.FEM_ERR_ARG
     with pytest.raises(fem.FemError):
         fem.BatchGraph([d], lanes=9, stream=0)
+
+
+def test_build_id_matches_sources(fem):
+    """The library reports the hash of the sources it was built from; a library
+    that is stale against the checkout's csrc/ and include/ fails here."""
+    from paper_1711_00903_amd import build
+    assert fem.fem_build_id() == build.source_hash(), \
+        "libfem.so was built from other sources: rebuild (__graft_entry__.build())"
+
+
+def test_vertex_applies_reject_overlapping_fields(fem):
+    """u and y of the vertex applies may not share bytes (partial overlap
+    included): a workgroup would overwrite another element's input."""
+    bad = 0x100000
+    E, N = 4, 7
+    nbytes = E * (N + 1) ** 3 * 8
+    for shift in (16, nbytes - 16, -(nbytes - 16)):
+        with pytest.raises(fem.FemError) as ei:
+            fem.fem_stiff_collocated_vertex_apply(N, E, bad, bad, 0.0, bad + 2 * nbytes,
+                                                  bad + 2 * nbytes + shift, stream=0)
+        assert ei.value.status == fem.FEM_ERR_ARG, shift
+        with pytest.raises(fem.FemError) as ei:
+            fem.fem_stiff_dealiased_vertex_apply(N, E, bad, bad, bad, 0.0, bad + 2 * nbytes,
+                                                 bad + 2 * nbytes + shift, stream=0)
+        assert ei.value.status == fem.FEM_ERR_ARG, shift
+
+
+def test_launch_size_limits(tmp_path):
+    """Work-item count of one dispatch stays below 2^32: the grid clamp and
+    the chunk loops of the element launchers (launch.hpp) cover every element
+    exactly once for any element count up to the advertised limit."""
+    import subprocess
+    src = tmp_path / "grid.cpp"
+    src.write_text(r'''
+#include <cstdio>
+#include "launch.hpp"
+int main() {
+    const int threads[] = {64, 128, 192, 256, 320, 384, 448, 512};
+    const long long Es[] = {1, 7, 65535, 16777216, 67108865, 2147483647LL};
+    for (int t : threads) {
+        const long long g = fem::max_grid(t);
+        if (g * t > 0xFFFFFFFFLL || (g + 1) * t <= 0xFFFFFFFFLL && g < 0x7FFFFFFFLL) { printf("bad %d\n", t); return 1; }
+        for (long long E : Es) {
+            // chunk loop of the line-per-lane launchers
+            long long covered = 0, launches = 0;
+            for (long long e0 = 0; e0 < E; e0 += g) {
+                const long long grid = E - e0 < g ? E - e0 : g;
+                if (grid * t > 0xFFFFFFFFLL || grid < 1) { printf("chunk %d %lld\n", t, E); return 1; }
+                covered += grid; ++launches;
+            }
+            if (covered != E) { printf("cover %d %lld\n", t, E); return 1; }
+        }
+    }
+    printf("ok\n");
+    return 0;
+}
+''')
+    exe = tmp_path / "grid"
+    csrc = os.path.join(ROOT, "paper_1711_00903_amd", "csrc")
+    subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", csrc,
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
+
+
+def test_assembly_inverse_map(fem):
+    """The inverse of a gather map groups each global node's local copies in
+    ascending order (a stable sort of the local indices by global node)."""
+    import workloads
+    gids, ng = workloads.global_numbering(3, 2, E=20)
+    off, loc = fem.fem_assembly_inverse_map(gids, ng)
+    order = np.argsort(gids.ravel(), kind="stable")
+    np.testing.assert_array_equal(loc, order)
+    np.testing.assert_array_equal(np.diff(off), np.bincount(gids.ravel(), minlength=ng))
+    assert off[0] == 0 and off[-1] == gids.size
+    bad = gids.copy()
+    bad[3, 5] = ng
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_assembly_inverse_map(bad, ng)
+    assert ei.value.status == fem.FEM_ERR_ARG
+
+
+def test_assembled_validation(fem):
+    bad = 0x1000
+    op = fem.CgOperator(N=3, E=8, I1d=bad, D1d=bad, G=bad, wJ=bad, lam=1.0)
+    asm = fem.Assembly(n_global=125, gather=bad, offsets=bad, locals=bad)
+    assert fem.fem_assembled_workspace_bytes(op, asm) > 0
+    asm.n_global = 8 * 64 + 1                                 # more global than local nodes
+    assert fem.fem_assembled_workspace_bytes(op, asm) == 0
+    asm.n_global = 125
+    opt = fem.CgOptions(mode=1, rtol=1e-8, max_iters=10)
+    with pytest.raises(fem.FemError) as ei:                  # FP64 only
+        fem.fem_pcg_solve(op, asm, opt, None, bad, bad + 4096, bad, 1 << 30, stream=0)
+    assert ei.value.status == fem.FEM_ERR_ARG
+    opt.mode = 0
+    with pytest.raises(fem.FemError) as ei:                  # workspace too small
+        fem.fem_pcg_solve(op, asm, opt, None, bad, bad + 4096, 1 << 20, 256, stream=0)
+    assert ei.value.status == fem.FEM_ERR_WORKSPACE
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_gather(64, 125, bad + 2, bad, 1 << 30, stream=0)
+    assert ei.value.status == fem.FEM_ERR_ALIGN

@@ -1,0 +1,82 @@
+"""The ragged-batch workload at full size against the oracle: 64 meshes
+(seed 355: degree N ~ U{1..15}, element count log-uniform in [64, 32768],
+operator uniform over BP1.0 / BP3.5 / BP3.0; mesh seed 1711 + m, field seed
+903 + m), FP64 and FP32 storage, applied by one replay of the captured graph
+(fem_batch_graph_*, 4 lanes).
+
+Every mesh's output is compared with the oracle on the same seeded inputs:
+all elements where the mesh has at most 2^20 local DOFs, else every k-th
+element plus the first and last 32 (elements are independent, so a subset is
+checked exactly).  FP64: relative L2 <= 1e-12 and per element <= 1e-11.
+FP32 storage: against the oracle applied to the FP32-rounded field and factors
+(oracle/storage.py), relative L2 <= 3e-5 and per element <= 3e-4 (the FP32
+arithmetic bound of tests/test_gpu_precision.py).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import storage
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FULL_DOFS = 1 << 20
+BARS = {0: (1e-12, 1e-11), 1: (3e-5, 3e-4)}
+
+
+def sample(E, Np):
+    if E * Np <= FULL_DOFS:
+        return np.arange(E)
+    k = max(1, (E * Np) // FULL_DOFS)
+    return np.unique(np.concatenate([np.arange(0, E, k), np.arange(min(E, 32)), np.arange(max(0, E - 32), E)]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ragged_batch_graph_matches_oracle(prec):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_00903_amd import fem
+    from paper_1711_00903_amd.mesh import DeviceMesh, FIELD_DTYPE, out_dtype
+    fem.lib()
+    spec = workloads.ragged_batch(64)
+    fmt = "f64" if prec == 0 else "f32"
+    descs, outs, keep, meta = [], [], [], []
+    for m in spec:
+        X = workloads.element_vertices(m.n, E=m.E, seed=m.mesh_seed)
+        dev = DeviceMesh(m.N, X, h=1.0 / m.n)
+        ut = torch.from_numpy(workloads.field(m.E, m.N + 1, seed=m.field_seed)).cuda().to(FIELD_DTYPE[prec])
+        yt = torch.zeros(ut.shape, dtype=out_dtype(prec), device="cuda")
+        descs.append(dev.desc(m.op, ut, yt, prec=prec))
+        outs.append(yt)
+        keep += [dev, ut]
+        meta.append(m)
+    stream = torch.cuda.Stream()
+    g = fem.BatchGraph(descs, lanes=4, stream=stream)
+    for rep in range(2):
+        for y in outs:
+            y.zero_()
+        torch.cuda.synchronize()
+        g.launch(stream=stream)
+        stream.synchronize()
+    g.destroy()
+    bar, per = BARS[prec]
+    worst = 0.0
+    for m, y in zip(meta, outs):
+        Np = (m.N + 1) ** 3
+        idx = sample(m.E, Np)
+        ys = y[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+        Xs = workloads.element_vertices_subset(m.n, idx, seed=m.mesh_seed)
+        us = storage.stored(workloads.field_rows(m.E, m.N + 1, idx, seed=m.field_seed), fmt)
+        if m.op == "BP10":
+            ref = oracle.bp10(m.N, storage.stored(oracle.geometry(m.N, Xs, "gl", want_G=False)[1], fmt), us)
+        elif m.op == "BP35":
+            ref = oracle.bp35(m.N, storage.stored(oracle.geometry(m.N, Xs, "gll", want_wJ=False)[0], fmt), us)
+        else:
+            ref = oracle.bp30(m.N, storage.stored(oracle.geometry(m.N, Xs, "gl", want_wJ=False)[0], fmt), us)
+        err = np.linalg.norm(ys - ref) / np.linalg.norm(ref)
+        elem = float(np.max(np.abs(ys - ref).max(axis=1) / np.abs(ref).max(axis=1)))
+        worst = max(worst, err)
+        assert err <= bar and elem <= per, (m, len(idx), err, elem)
+    print(f"ragged batch prec={prec}: 64 meshes, worst rel-L2 {worst:.3e}", flush=True)

@@ -131,3 +131,38 @@ def test_bad_arguments(setup):
     with pytest.raises(fem.FemError) as ei:
         fem.fem_cg_solve(op, opt, bt, bt.clone(), ws, nb - 256)
     assert ei.value.status == fem.FEM_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("inner", [6, 7])
+def test_iterative_refinement_converges(setup, inner):
+    """Mode 2 (the inner CG restarted at every FP64 residual replacement) with
+    narrow geometric data and FP64 vectors reaches the tolerance; the oracle
+    confirms the residual."""
+    fem, dev, bt, bo, A = setup
+    rtol = 1e-8
+    rep, x = solve(setup, 2, inner, rtol, history=256)
+    hist = rep.pop("history")
+    print(f"IR inner={inner}: {rep}")
+    assert rep["status"] == fem.FEM_OK and rep["rel_res"] <= rtol
+    assert len(hist) == rep["reliable_updates"] + 1
+    assert true_relative_residual(A, bo, x.cpu().numpy()) <= 1.1 * rtol
+
+
+@pytest.mark.parametrize("inner", [1, 4, 5])
+def test_iterative_refinement_fp32_inner(setup, inner):
+    """FP32 vectors and arithmetic in the inner CG (u, G stored FP32, BF16 or
+    FP16) with lambda = 4096 (condition number ~1e3, so kappa * eps32 << 1):
+    the refinement reaches 1e-8; the oracle confirms the residual, and the
+    reported residual is the true one."""
+    fem, dev, bt, bo, A = setup
+    lam, rtol = 4096.0, 1e-8
+    X = workloads.element_vertices(NGRID, E=E)
+    pb = oracle.Problem(N, X)
+    A4 = lambda v: pb.cg_operator(v, lam)
+    x = torch.zeros_like(bt)
+    rep = dev.cg_solve(bt, x, lam=lam, mode=2, inner_prec=inner, rtol=rtol, delta=0.1, max_iters=5000)
+    torch.cuda.synchronize()
+    print(f"IR FP32 inner={inner}: {rep}")
+    res = true_relative_residual(A4, bo, x.cpu().numpy())
+    assert abs(rep["rel_res"] - res) <= 1e-3 * res + 1e-14
+    assert rep["status"] == fem.FEM_OK and res <= 1.1 * rtol, (rep, res)

@@ -270,33 +270,6 @@ def test_vertex_geometry_dealiased(fem, DeviceMesh, N):
     compare(yt, oracle_apply("BP30", N, X, u, lam) + beta * y0, f"BP30 vertices lambda/beta N={N}")
 
 
-# ---------------------------------------------------------------- reduced precision
-
-# Error of storage-rounded inputs with FP32 arithmetic, against the FP64 oracle.
-# Not a parity bar: an upper bound on the reported error (unit roundoff of the
-# storage format times a modest amplification by the stiffness operators).
-PREC_BOUND = {1: 2e-5, 2: 6e-2, 3: 1e-2, 4: 6e-2, 5: 1e-2, 6: 2e-5, 7: 6e-2, 8: 1e-2}
-
-
-@pytest.mark.parametrize("prec", [1, 2, 3, 4, 5, 6, 7, 8])
-@pytest.mark.parametrize("op", ["BP10", "BP35", "BP30"])
-@pytest.mark.parametrize("N", [3, 7])
-def test_reduced_precision_error(fem, DeviceMesh, prec, op, N):
-    from paper_1711_00903_amd.mesh import FIELD_DTYPE
-    X, n = mesh_elems(64)
-    E = X.shape[0]
-    u = workloads.field(E, N + 1, seed=21)
-    dev = DeviceMesh(N, X, h=1.0 / n)
-    ut = torch.from_numpy(u).cuda().to(FIELD_DTYPE[prec])
-    y = gpu_apply(dev, op, ut, prec=prec)
-    torch.cuda.synchronize()
-    assert y.dtype == (torch.float64 if prec >= 6 else torch.float32)
-    ref = oracle_apply(op, N, X, u)
-    err = np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref)
-    print(f"{op} N={N} prec={prec}: rel-L2 vs FP64 oracle {err:.3e}")
-    assert err <= PREC_BOUND[prec]
-
-
 # ---------------------------------------------------------------- full-size workloads
 
 def test_full_size_bp35_n7_e32768(fem, DeviceMesh):

@@ -9,6 +9,10 @@ basis tables, no geometric factors and no operator.  It produces only
   the reference cube through its 8 vertices, Problem description section);
 * the element-to-vertex gathering of that grid (element vertex order
   ``a + 2 b + 4 c`` for the corner at ``r = +-1, s = +-1, t = +-1``);
+* the global numbering of the degree-N tensor nodes of that grid: local node
+  ``(i, j, k)`` of element ``(ex, ey, ez)`` is lattice point
+  ``(N ex + i, N ey + j, N ez + k)``, so nodes on shared faces, edges and
+  corners get one global number (connectivity only);
 * uniform random fields ``u`` over the local nodes of each element;
 * the random noise and the random mesh descriptors of the batched workload.
 
@@ -95,6 +99,51 @@ def element_vertices_subset(n: int, elems: np.ndarray, V: np.ndarray | None = No
     return out
 
 
+def global_numbering(n: int, N: int, E: int | None = None) -> tuple[np.ndarray, int]:
+    """Global node numbers of the first ``E`` elements of the ``n^3`` grid at
+    degree N: ``(gids (E, (N+1)^3) int32, n_global)``.
+
+    Local node ``i + Nq j + Nq^2 k`` of element ``e = ex + n (ey + n ez)`` is
+    the lattice point ``(N ex + i, N ey + j, N ez + k)`` of the
+    ``(N n + 1)^3`` node lattice; the lattice points the elements touch are
+    numbered 0.. in lexicographic order (z slowest), so a partial grid has no
+    unused numbers.
+    """
+    if E is None:
+        E = n ** 3
+    Nq = N + 1
+    L = N * n + 1
+    e = np.arange(E, dtype=np.int64)
+    ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+    k, j, i = np.meshgrid(np.arange(Nq), np.arange(Nq), np.arange(Nq), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()              # local node i + Nq j + Nq^2 k
+    lat = ((N * ex[:, None] + i) + L * ((N * ey[:, None] + j) + L * (N * ez[:, None] + k)))
+    used = np.zeros(L ** 3, dtype=bool)
+    used[lat.ravel()] = True
+    rank = np.cumsum(used, dtype=np.int64) - 1              # number of each used lattice point
+    ng = int(rank[-1]) + 1
+    if ng >= 2 ** 31:
+        raise ValueError("more global nodes than int32 numbers")
+    return rank[lat].astype(np.int32), ng
+
+
+def global_lattice_coords(n: int, N: int, E: int | None = None) -> np.ndarray:
+    """Integer lattice coordinates ``(n_global, 3)`` (x, y, z index on the
+    ``(N n + 1)^3`` lattice) of each global node of :func:`global_numbering`."""
+    if E is None:
+        E = n ** 3
+    gids, ng = global_numbering(n, N, E)
+    Nq = N + 1
+    e = np.arange(E, dtype=np.int64)
+    ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+    k, j, i = np.meshgrid(np.arange(Nq), np.arange(Nq), np.arange(Nq), indexing="ij")
+    out = np.empty((ng, 3), dtype=np.int64)
+    out[gids, 0] = N * ex[:, None] + i.ravel()
+    out[gids, 1] = N * ey[:, None] + j.ravel()
+    out[gids, 2] = N * ez[:, None] + k.ravel()
+    return out
+
+
 def field(E: int, Nq: int, seed: int = SEED_FIELD) -> np.ndarray:
     """``u ~ U[-1, 1]`` per local node, shape ``(E, Nq^3)``, node ``i + Nq j + Nq^2 k``."""
     rng = np.random.default_rng(seed)
@@ -127,6 +176,11 @@ def field_chunked(E: int, Nq: int, seed: int = SEED_FIELD, chunk: int = 4096):
     for start in range(0, E, chunk):
         stop = min(E, start + chunk)
         yield start, rng.uniform(-1.0, 1.0, size=(stop - start, Nq ** 3))
+
+
+def global_noise(n_global: int, seed: int = SEED_RHS_NOISE) -> np.ndarray:
+    """Noise ``U[-1, 1]`` per global node, shape ``(n_global,)`` (scaled by the caller)."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n_global)
 
 
 def rhs_noise(E: int, Nq: int, seed: int = SEED_RHS_NOISE) -> np.ndarray:
