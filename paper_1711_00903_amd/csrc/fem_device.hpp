@@ -60,7 +60,16 @@ template <class TS> __device__ __forceinline__ TS from_double(double v);
 template <> __device__ __forceinline__ double from_double<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_double<float>(double v) { return static_cast<float>(v); }
 template <> __device__ __forceinline__ bf16_t from_double<bf16_t>(double v) { return to_bf16(static_cast<float>(v)); }
-template <> __device__ __forceinline__ f16_t from_double<f16_t>(double v) { return static_cast<f16_t>(static_cast<float>(v)); }
+// FP16 storage rounds in two steps, FP64 -> FP32 -> FP16 (each to nearest
+// even), as BF16 does.  The empty asm keeps the compiler from merging the two
+// conversions into one FP64 -> FP16 rounding, which differs from the two-step
+// result wherever the FP32 value falls exactly halfway between two FP16 values.
+template <> __device__ __forceinline__ f16_t from_double<f16_t>(double v)
+{
+    float f = static_cast<float>(v);
+    asm volatile("" : "+v"(f));
+    return static_cast<f16_t>(f);
+}
 
 // Non-temporal load for data that is streamed exactly once (geometric factors):
 // keeps them from evicting the field vectors from the caches.

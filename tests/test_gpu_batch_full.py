@@ -9,8 +9,10 @@ all elements where the mesh has at most 2^20 local DOFs, else every k-th
 element plus the first and last 32 (elements are independent, so a subset is
 checked exactly).  FP64: relative L2 <= 1e-12 and per element <= 1e-11.
 FP32 storage: against the oracle applied to the FP32-rounded field and factors
-(oracle/storage.py), relative L2 <= 3e-5 and per element <= 3e-4 (the FP32
-arithmetic bound of tests/test_gpu_precision.py).
+(oracle/storage.py), relative L2 <= 3e-5 and per element <= 3e-4: the a priori
+FP32 arithmetic bound (at most seven one-direction sums of at most 17 terms,
+7 * 17 * 2^-24 = 7e-6 of the absolute terms), kept here because the batch
+spans mesh sizes the measured bound of tests/test_gpu_precision.py does not.
 """
 import numpy as np
 import pytest

@@ -9,14 +9,15 @@ compared with that, element by element:
 * modes with FP64 fields and FP64 arithmetic (F32G64, BF16G64, F16G64): the
   FP64 bar, relative L2 <= 1e-12 and per element <= 1e-11 of the element's
   largest output;
-* modes with FP32 arithmetic (F32, BF16, F16, BF16G, F16G): a bound derived
-  from FP32 arithmetic.  An output passes through at most seven one-direction
-  sums of at most 17 terms (BP3.0 at N = 15: three interpolations, a
-  derivative, the metric step, three transposes folded with the projection),
-  so its rounding error is at most about 7 * 17 * 2^-24 = 7e-6 of the sum of
-  the absolute terms; the random fields make that sum at most a few times
-  |y|.  Bound: relative L2 <= 3e-5, per element <= 3e-4.  The FP32 result y
-  adds one rounding (6e-8).
+* modes with FP32 arithmetic (F32, BF16, F16, BF16G, F16G): the FP32
+  arithmetic is then the only difference.  A priori an output passes through
+  at most seven one-direction sums of at most 17 terms (BP3.0 at N = 15), so
+  its rounding error is at most about 7 * 17 * 2^-24 = 7e-6 of the sum of the
+  absolute terms.  Measured over every mode, operator and degree here (the
+  table FEM_RECORD_DIR receives, kept in profiles/): at most 2.8e-7 relative
+  L2 and 7.1e-7 per element, so the bound is about three times that:
+  relative L2 <= 8e-7, per element <= 2e-6.  A result rounded once more than
+  it should be, or scaled wrongly, exceeds it.
 
 The error of each result against the FP64 oracle on the *unrounded* inputs --
 the error the storage format costs -- is recorded per (mode, operator, N).
@@ -41,7 +42,7 @@ MODES = {1: ("f32", "f32", "f32"), 2: ("bf16", "bf16", "f32"), 3: ("f16", "f16",
          4: ("f32", "bf16", "f32"), 5: ("f32", "f16", "f32"),
          6: ("f64", "f32", "f64"), 7: ("f64", "bf16", "f64"), 8: ("f64", "f16", "f64")}
 MODE_NAMES = {1: "F32", 2: "BF16", 3: "F16", 4: "BF16G", 5: "F16G", 6: "F32G64", 7: "BF16G64", 8: "F16G64"}
-BAR = {"f64": (1e-12, 1e-11), "f32": (3e-5, 3e-4)}
+BAR = {"f64": (1e-12, 1e-11), "f32": (8e-7, 2e-6)}
 E = 64
 ROWS = []
 
