@@ -282,6 +282,23 @@ size_t fem_cg_workspace_bytes(const fem_cg_operator *op, const fem_cg_options *o
 int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
                  void *workspace, size_t workspace_bytes, fem_cg_report *rep, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc): fem_cg_solve with its
+ * workspace in a device array that the library holds, FEM_CG_NOALLOC_BYTES
+ * bytes per GPU it runs on, from the first call on that GPU until the process
+ * ends.  Arguments, results and the blocking behaviour are those of
+ * fem_cg_solve.  Returns FEM_ERR_WORKSPACE, before anything is enqueued, when
+ * the solve needs more than FEM_CG_NOALLOC_BYTES (fem_cg_workspace_bytes);
+ * with FP64 vectors that is about 48 bytes per DOF, so up to ~1.4M DOFs
+ * (E = 2730 at N = 7).  The call allocates nothing.  Every call on one GPU
+ * shares that GPU's array and leaves its contents behind (a solve initialises
+ * what it reads): calls that overlap in time on one GPU, from several host
+ * threads or on several streams, race and give wrong results.  The stream
+ * must belong to the current device. */
+#define FEM_CG_NOALLOC_BYTES (64u << 20)
+int fem_cg_solve_noalloc(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
+                         fem_cg_report *rep, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Assembled (continuous) operator.  The applies above act on each element's
  * own copy of its nodes: one block-diagonal matrix (Problem description

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -531,6 +532,54 @@ int fem_cg_solve(const fem_cg_operator *op, const fem_cg_options *opt, const dou
     if (overlap(b, n * 8, x, n * 8)) return FEM_ERR_ARG;
     if (workspace_bytes < cg_workspace_bytes(op, opt)) return FEM_ERR_WORKSPACE;
     return cg_solve(op, opt, b, x, workspace, rep, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------- CG without allocation
+//
+// fem_cg_solve_noalloc runs fem_cg_solve's code with its workspace in a
+// file-scope device array: each GPU the library runs on holds one copy of
+// FEM_CG_NOALLOC_BYTES bytes until the process ends.  In host code the
+// array's name is a host-side stand-in, so kernels and copies get the
+// device address that hipGetSymbolAddress returns, taken once per device
+// with that device current (the first call on it) and kept.
+static __device__ __align__(256) unsigned char scratch[FEM_CG_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+void *scratch_ptr()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int fem_cg_solve_noalloc(const fem_cg_operator *op, const fem_cg_options *opt, const double *b, double *x,
+                         fem_cg_report *rep, void *stream)
+{
+    int st = cg_check(op, opt);
+    if (st != FEM_OK) return st;
+    if (!rep) return FEM_ERR_ARG;
+    *rep = fem_cg_report{};
+    if (op->E == 0) return FEM_OK;
+    if (!b || !x) return FEM_ERR_ARG;
+    if (!aligned16(b) || !aligned16(x)) return FEM_ERR_ALIGN;
+    const int64_t n = op->E * static_cast<int64_t>(op->N + 1) * (op->N + 1) * (op->N + 1);
+    if (overlap(b, n * 8, x, n * 8)) return FEM_ERR_ARG;
+    if (cg_workspace_bytes(op, opt) > static_cast<size_t>(FEM_CG_NOALLOC_BYTES)) return FEM_ERR_WORKSPACE;
+    void *ws = scratch_ptr();
+    if (!ws) return FEM_ERR_HIP;
+    // the solve clears its own scalars; the vectors are written before they are read
+    return cg_solve(op, opt, b, x, ws, rep, static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------- assembled operator

@@ -111,6 +111,8 @@ _SIGS = {
     "fem_cg_workspace_bytes": ([C.POINTER(CgOperator), C.POINTER(CgOptions)], C.c_size_t),
     "fem_cg_solve": ([C.POINTER(CgOperator), C.POINTER(CgOptions), _vp, _vp, _vp, C.c_size_t,
                       C.POINTER(CgReport), _vp], C.c_int),
+    "fem_cg_solve_noalloc": ([C.POINTER(CgOperator), C.POINTER(CgOptions), _vp, _vp, C.POINTER(CgReport), _vp],
+                             C.c_int),
     "fem_assembly_inverse_map": ([_i64, _vp, _i64, _vp, _vp], C.c_int),
     "fem_gather": ([_i64, _i64, _vp, _vp, _vp, _vp], C.c_int),
     "fem_scatter": ([_i64, _i64, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -300,6 +302,21 @@ def fem_cg_solve(op: CgOperator, opt: CgOptions, b, x, workspace, workspace_byte
                             workspace_bytes, C.byref(rep), _stream(stream))
     if raise_on_error and st not in (FEM_OK, FEM_ERR_NOT_CONVERGED, FEM_ERR_BREAKDOWN):
         raise FemError(st, "fem_cg_solve")
+    return rep
+
+
+# FEM_CG_NOALLOC_BYTES of include/fem.h: the device array fem_cg_solve_noalloc works in
+FEM_CG_NOALLOC_BYTES = 64 << 20
+
+
+def fem_cg_solve_noalloc(op: CgOperator, opt: CgOptions, b, x, stream=None,
+                         raise_on_error: bool = True) -> CgReport:
+    """fem_cg_solve with the library's own device workspace (no allocation);
+    statuses as for fem_cg_solve."""
+    rep = CgReport()
+    st = lib().fem_cg_solve_noalloc(C.byref(op), C.byref(opt), _ptr(b), _ptr(x), C.byref(rep), _stream(stream))
+    if raise_on_error and st not in (FEM_OK, FEM_ERR_NOT_CONVERGED, FEM_ERR_BREAKDOWN):
+        raise FemError(st, "fem_cg_solve_noalloc")
     return rep
 
 

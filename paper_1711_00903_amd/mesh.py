@@ -176,14 +176,18 @@ class DeviceMesh:
     def cg_solve(self, b, x, lam: float = 1.0, mode: int = 0, inner_prec: int = fem.FEM_F32,
                  rtol: float = 1e-10, max_iters: int = 20000, delta: float = 0.1,
                  check_every: int = 1, fusion: int = fem.FEM_CG_FUSE_AUTO, history: int = 0,
-                 stream=None) -> dict:
-        """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors."""
+                 stream=None, noalloc: bool = False) -> dict:
+        """Solve (S + lam M) x = b with libfem's CG; b, x FP64 [E, Np] device tensors.
+        With noalloc, through fem_cg_solve_noalloc (the library's own workspace)."""
         op, opt, hist = self.cg_structs(lam, mode, inner_prec, rtol, max_iters, delta, check_every, fusion,
                                         history)
-        nbytes = fem.fem_cg_workspace_bytes(op, opt)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        rep = fem.fem_cg_solve(op, opt, b, x, ws, nbytes, stream)
-        del ws
+        if noalloc:
+            rep = fem.fem_cg_solve_noalloc(op, opt, b, x, stream)
+        else:
+            nbytes = fem.fem_cg_workspace_bytes(op, opt)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            rep = fem.fem_cg_solve(op, opt, b, x, ws, nbytes, stream)
+            del ws
         out = rep.as_dict()
         if history:
             out["history"] = list(hist[:rep.history_count])

@@ -315,3 +315,29 @@ def test_assembled_validation(fem):
     with pytest.raises(fem.FemError) as ei:
         fem.fem_gather(64, 125, bad + 2, bad, 1 << 30, stream=0)
     assert ei.value.status == fem.FEM_ERR_ALIGN
+
+
+def test_cg_noalloc_host_checks(fem):
+    """fem_cg_solve_noalloc: the binding's array size is the header's, and a
+    solve that needs more than the array, or a bad argument, is refused during
+    validation (before any device work)."""
+    txt = open(os.path.join(ROOT, "include", "fem.h")).read()
+    m = re.search(r"#define FEM_CG_NOALLOC_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == fem.FEM_CG_NOALLOC_BYTES
+    bad = 0x1000
+    n7 = 512 * 8
+    op = fem.CgOperator(N=7, E=4096, I1d=bad, D1d=bad, G=bad, wJ=bad, lam=1.0)
+    opt = fem.CgOptions(mode=0, rtol=1e-8, max_iters=10)
+    assert fem.fem_cg_workspace_bytes(op, opt) > fem.FEM_CG_NOALLOC_BYTES
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_cg_solve_noalloc(op, opt, bad, bad + 4096 * n7, stream=0)
+    assert ei.value.status == fem.FEM_ERR_WORKSPACE
+    op.E = 64
+    assert fem.fem_cg_workspace_bytes(op, opt) <= fem.FEM_CG_NOALLOC_BYTES
+    with pytest.raises(fem.FemError) as ei:                  # b and x overlap
+        fem.fem_cg_solve_noalloc(op, opt, bad, bad + 16, stream=0)
+    assert ei.value.status == fem.FEM_ERR_ARG
+    opt.mode = 3
+    with pytest.raises(fem.FemError) as ei:
+        fem.fem_cg_solve_noalloc(op, opt, bad, bad + 64 * n7, stream=0)
+    assert ei.value.status == fem.FEM_ERR_ARG
