@@ -122,7 +122,15 @@ int supported_epb(int op, int N, int prec, int *out, int cap)
 int default_epb(int op, int N, int prec)
 {
     (void)prec;
-    return epb_default(op, N + 1);
+    // memoised like kernel_info below (the shape model is costly to evaluate)
+    static std::atomic<int> memo[3][kMaxN + 1];
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN) return epb_default(op, N + 1);
+    int v = memo[op][N].load(std::memory_order_acquire);
+    if (v == 0) {
+        v = epb_default(op, N + 1);
+        memo[op][N].store(v, std::memory_order_release);
+    }
+    return v;
 }
 
 static int geo_value_bytes(int prec)
@@ -134,7 +142,7 @@ static int geo_value_bytes(int prec)
     }
 }
 
-bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
+static bool kernel_info_eval(int op, int N, int prec, int epb, KernelInfo *info)
 {
     int ch[kMaxEpbChoices];
     const int n = supported_epb(op, N, prec, ch, kMaxEpbChoices);
@@ -145,6 +153,33 @@ bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
     const int bytes = f64_fields(prec) ? 8 : 4;   // compute type held in LDS
     info->threads = threads_for(op, N + 1, epb);
     info->lds_bytes = lds_bytes(op, N + 1, epb, bytes, geo_value_bytes(prec));
+    return true;
+}
+
+// Every apply validates its launch shape, and evaluating the shape model
+// (the LDS row padding simulates bank conflicts) costs about 0.1 ms on the
+// host -- far more than the launch itself.  The result depends only on
+// (op, N, prec, epb), so it is computed once per key and kept: 0 = not yet
+// known, -1 = unsupported, else (threads << 32 | LDS bytes).  Two threads may
+// both compute a key; they store the same value.
+constexpr int kMemoEpb = 64;
+static std::atomic<int64_t> g_kinfo[3][kMaxN + 1][P_COUNT][kMemoEpb + 1];
+
+bool kernel_info(int op, int N, int prec, int epb, KernelInfo *info)
+{
+    if (op < 0 || op > 2 || N < 1 || N > kMaxN || prec < 0 || prec >= P_COUNT) return false;
+    if (epb == 0) epb = default_epb(op, N, prec);
+    if (epb < 1 || epb > kMemoEpb) return false;
+    std::atomic<int64_t> &slot = g_kinfo[op][N][prec][epb];
+    int64_t v = slot.load(std::memory_order_acquire);
+    if (v == 0) {
+        KernelInfo ki{};
+        v = kernel_info_eval(op, N, prec, epb, &ki) ? (static_cast<int64_t>(ki.threads) << 32) | ki.lds_bytes : -1;
+        slot.store(v, std::memory_order_release);
+    }
+    if (v < 0) return false;
+    info->threads = static_cast<int>(v >> 32);
+    info->lds_bytes = static_cast<int>(v & 0xFFFFFFFF);
     return true;
 }
 
