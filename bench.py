@@ -50,8 +50,8 @@ KERNEL_SOURCES = {
     "BP35": ["bp35.hpp", "bp35t.hpp", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
     "BP10": ["bp10.hpp", "bp10t.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
              "launch.hpp"],
-    "BP30": ["bp30.hpp", "bp30t.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
-             "launch.hpp"],
+    "BP30": ["bp30.hpp", "bp30t.hpp", "bp30t2.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp",
+             "tiles.hpp", "launch.hpp"],
     "BP35V": ["bp35v.hip", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
     "BP30V": ["bp30v.hip", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
 }
@@ -233,7 +233,7 @@ def cg_arms(grid: int, lam: float, rtol: float, arm_names: list[str], solves: in
     for _, mode, prec in arms:   # all geometric data built before any timing
         dev.geometry(fem.FEM_QUAD_GLL, fem.FEM_F64, want_wJ=False)
         dev.geometry(fem.FEM_QUAD_GL, fem.FEM_F64, want_G=False, kind="wJ")
-        if mode == 1:
+        if mode in (1, 2):
             dev.geometry(fem.FEM_QUAD_GLL, prec, want_wJ=False)
             dev.geometry(fem.FEM_QUAD_GL, prec, want_G=False, kind="wJ")
     torch.cuda.synchronize()
@@ -445,24 +445,112 @@ def run_sweep(args) -> int:
     recs = tune.autotune(X, ops=tuple(args.sweep_ops.split(",")), Ns=Ns, precs=precs,
                          reps=args.sweep_reps, h=1.0 / args.sweep_grid, log=log)
     for r in recs:
-        r["frac_of_copy"] = r["gbs"] / copy["best"]
-        r["frac_of_peak"] = r["gbs"] / HBM_PEAK_GBS
-        # the empirical model's two bounds on the apply time (eqs. globalRoof,
-        # sharedRoof): HBM bytes over the copy rate, LDS bytes over B_sh (the
-        # 8-byte read rate: the kernels' LDS accesses are 8-byte or narrower)
-        nb = tune.alg_bytes(r["op"], r["N"], r["E"], r["prec"])
-        lb = tune.lds_bytes(r["op"], r["N"], r["E"], r["prec"], r["epb"])
-        r["kernel"] = tune.kernel_family(r["op"], r["N"], r["epb"])
-        r["lds_bytes"] = lb
-        r["t_hbm_ms"] = nb / (copy["best"] * 1e9) * 1e3
-        r["t_lds_ms"] = lb / (lds["read_b64_GB/s"] * 1e9) * 1e3
-        r["t_model_ms"] = max(r["t_hbm_ms"], r["t_lds_ms"])
-        r["frac_of_model"] = r["t_model_ms"] / r["ms"]
+        model_columns(r, copy["best"], lds)
     if args.tune_out:
         with open(args.tune_out, "w") as f:
             f.write(tune.table_text(recs))
     print(json.dumps({"workload": f"sweep_e{X.shape[0]}", "E": X.shape[0], "copy_roofline": copy,
                       "lds_roofline": lds, "records": recs}), flush=True)
+    return 0
+
+
+def model_columns(r: dict, copy_gbs: float, lds: dict) -> None:
+    """The empirical model's two bounds on one apply (eqs. globalRoof and
+    sharedRoof): HBM time = algorithmic bytes / B_copy; LDS time = the values
+    the kernel's schedule reads and writes in LDS (s_r, s_w, tune.lds_values)
+    over the measured 8-byte LDS read and write rates (the kernels' LDS
+    accesses are 8 bytes wide or narrower).  The model time is the larger, so
+    the rate bound is min(R_global, R_shared); the vector-ALU time of the
+    algorithmic flops is reported beside them as a third ceiling."""
+    from paper_1711_00903_amd import tune
+    nb = tune.alg_bytes(r["op"], r["N"], r["E"], r["prec"])
+    fam = tune.kernel_family(r["op"], r["N"], r["epb"], r["prec"])
+    sr, sw = tune.lds_values(fam, r["N"])
+    vb = 8 if r["prec"] in tune._F64_FIELDS else 4
+    r["kernel"] = fam
+    r["frac_of_copy"] = r["gbs"] / copy_gbs
+    r["frac_of_peak"] = r["gbs"] / HBM_PEAK_GBS
+    r["lds_bytes"] = r["E"] * (sr + sw) * vb
+    r["t_hbm_ms"] = nb / (copy_gbs * 1e9) * 1e3
+    r["t_lds_ms"] = r["E"] * (sr * vb / (lds["read_b64_GB/s"] * 1e9) + sw * vb / (lds["write_b64_GB/s"] * 1e9)) * 1e3
+    # a third ceiling, not in the paper's model: the algorithmic flops (no
+    # even-odd saving) at the vector peak of the arithmetic type
+    r["t_alu_ms"] = tune.alg_flops(r["op"], r["N"], r["E"]) / ((FP64_PEAK_TFLOPS if vb == 8 else 157.3) * 1e12) * 1e3
+    t = {"hbm": r["t_hbm_ms"], "lds": r["t_lds_ms"], "alu": r["t_alu_ms"]}
+    r["bound"] = max(t, key=t.get)
+    r["t_model_ms"] = t[r["bound"]]
+    r["frac_of_model"] = r["t_model_ms"] / r["ms"]
+
+
+def sweep_markdown(paths: list[str]) -> str:
+    """Markdown summary of sweep records (bench.py --sweep JSON lines); a
+    later file replaces the records of the (operator, N, precision) it
+    covers.  The model columns are recomputed with each file's own copy and
+    LDS rates."""
+    from paper_1711_00903_amd import fem
+    recs, notes = {}, []
+    for path in paths:
+        with open(path) as f:
+            d = json.loads(f.read().strip().splitlines()[-1])
+        notes.append(f"* `{os.path.basename(path)}`: copy {d['copy_roofline']['best']:.0f} GB/s, LDS 8-byte "
+                     f"reads {d['lds_roofline']['read_b64_GB/s'] / 1e3:.1f} TB/s, writes "
+                     f"{d['lds_roofline']['write_b64_GB/s'] / 1e3:.1f} TB/s")
+        for r in d["records"]:
+            model_columns(r, d["copy_roofline"]["best"], d["lds_roofline"])
+            recs[(r["prec"], r["op"], r["N"])] = r
+    names = {v: k for k, v in fem.PREC_NAMES.items()}
+    out = ["Inputs (each with its measured rates):", *notes, ""]
+    for prec in sorted({k[0] for k in recs}):
+        out += [f"## {names[prec]}", "",
+                "| N | op | kernel | epb / cap | ms | GB/s | % copy | % 8 TB/s | GDOF/s | t_HBM ms | t_LDS ms | "
+                "t_ALU ms | bound | % of model |", "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+        for (p, op, N) in sorted(k for k in recs if k[0] == prec):
+            r = recs[(p, op, N)]
+            out.append(f"| {N} | {op} | {r['kernel']} | {r['epb']} / {r['grid_cap']} | {r['ms']:.4f} | "
+                       f"{r['gbs']:.0f} | {100 * r['frac_of_copy']:.0f}% | {100 * r['frac_of_peak']:.0f}% | "
+                       f"{r['gdofs']:.1f} | {r['t_hbm_ms']:.4f} | {r['t_lds_ms']:.4f} | {r['t_alu_ms']:.4f} | {r['bound']} | "
+                       f"{100 * r['frac_of_model']:.0f}% |")
+        out.append("")
+    return "\n".join(out)
+
+
+def run_case(args) -> int:
+    """One operator at one degree and storage precision on the sweep mesh
+    (64^3 by default): warm-up, then K back-to-back applies timed with events,
+    for rocprofv3 kernel traces and counters of a single kernel."""
+    import torch
+
+    import workloads
+    from paper_1711_00903_amd import fem, tune
+    from paper_1711_00903_amd.mesh import DeviceMesh, FIELD_DTYPE, out_dtype
+
+    fem.lib()
+    op, Nc, pname = args.case.split(":")
+    Nc = int(Nc)
+    prec = fem.PREC_NAMES[pname]
+    X = workloads.element_vertices(args.sweep_grid)
+    dev = DeviceMesh(Nc, X, h=1.0 / args.sweep_grid)
+    E = dev.E
+    u = torch.from_numpy(workloads.field(E, Nc + 1)).cuda().to(FIELD_DTYPE[prec])
+    y = torch.empty((E, dev.np), dtype=out_dtype(prec), device="cuda")
+    call = {"BP10": lambda: dev.mass(u, y=y, prec=prec), "BP35": lambda: dev.stiff35(u, y=y, prec=prec),
+            "BP30": lambda: dev.stiff30(u, y=y, prec=prec)}[op]
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nb = tune.alg_bytes(op, Nc, E, prec)
+    opid = fem.OP_NAMES[op]
+    epb, cap = fem.fem_tune_get(opid, Nc, prec)
+    print(json.dumps({"case": args.case, "E": E, "epb": epb, "grid_cap": cap,
+                      "kernel": tune.kernel_family(op, Nc, epb or 1, prec), "ms": ms, "alg_bytes": nb,
+                      "GB/s": nb / (ms * 1e-3) / 1e9, "GDOF/s": E * dev.np / (ms * 1e-3) / 1e9}), flush=True)
     return 0
 
 
@@ -571,6 +659,11 @@ def main() -> int:
     ap.add_argument("--sweep-ops", default="BP10,BP35,BP30")
     ap.add_argument("--sweep-reps", type=int, default=10)
     ap.add_argument("--tune-out", default="")
+    ap.add_argument("--sweep-md", default="",
+                    help="comma-separated sweep JSON files: print their merged markdown summary and exit")
+    ap.add_argument("--case", default="",
+                    help="OP:N:PREC (e.g. BP30:10:f64): K applies of that operator's tuned kernel on the "
+                         "--sweep-grid mesh, for profiling; prints the mean kernel time")
     ap.add_argument("--batch", action="store_true", help="ragged batch: eager vs captured graph")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-precs", default="f64,f32")
@@ -588,6 +681,9 @@ def main() -> int:
         copy = copy_roofline(fem, torch, 1 << 30, settle_s=0.5)
         print(json.dumps({"lds_roofline": lds_roofline(fem, torch), "copy_roofline": copy}), flush=True)
         return 0
+    if args.sweep_md:
+        print(sweep_markdown(args.sweep_md.split(",")))
+        return 0
     if args.sweep:
         return run_sweep(args)
     if args.batch:
@@ -596,6 +692,8 @@ def main() -> int:
         return run_cg(args)
     if args.pcg:
         return run_pcg(args)
+    if args.case:
+        return run_case(args)
 
     import torch
 
@@ -683,6 +781,25 @@ def main() -> int:
         e.record(stream)
     torch.cuda.synchronize()
     per = np.array([s.elapsed_time(e) for s, e in pairs])
+    # the same K launches replayed from one captured graph (no host in the
+    # loop): separates the kernels' own time from what the eager dispatch of
+    # dependent launches adds between them
+    graph_ms = None
+    if op in ("BP35", "BP10", "BP30"):
+        gstream = torch.cuda.Stream()
+        descs = [dev.desc(op, ut, y) for _ in range(args.steps)]
+        g = fem.BatchGraph(descs, lanes=1, stream=gstream)
+        for _ in range(2):
+            g.launch(gstream)
+        gstream.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record(gstream)
+        g.launch(gstream)
+        g1.record(gstream)
+        g1.synchronize()
+        graph_ms = g0.elapsed_time(g1) / args.steps
+        g.destroy()
+        log(f"bench: {args.steps} launches from one graph: {graph_ms:.4f} ms per launch")
     copy_after = copy_roofline(fem, torch, bytes_launch)
     log(f"bench: copy roofline after {copy_after}")
     copy_best = max(copy_before["best"], copy_after["best"])
@@ -755,6 +872,7 @@ def main() -> int:
                      "per_launch_ms": {"launches": npl, "median": float(np.median(per)), "mean": float(per.mean()),
                                        "min": float(per.min()), "max": float(per.max()),
                                        "source": "event pair around each launch, after the timed region"},
+                     "graph_ms_per_launch": graph_ms,
                      "alg_bytes_per_launch": bytes_launch},
         "copy_roofline": {"GB/s": copy_best, "before_GB/s": copy_before["best"], "after_GB/s": copy_after["best"],
                           "kernel_GB/s": max(copy_before["kernel"], copy_after["kernel"]),

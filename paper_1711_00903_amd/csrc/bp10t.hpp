@@ -52,7 +52,10 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     constexpr int NP = NC * NQ;
     constexpr int NPG = NG * NG * NG;
     constexpr int HG = (NG + 1) / 2, HQ = (NQ + 1) / 2, GE = NG / 2, QE = NQ / 2;
-    constexpr int P = lds_row(NQ, sizeof(TC));   // row length of both LDS volumes (rows along i)
+    // row length of both LDS volumes (rows along i); FP64 at Nq = 16 takes odd
+    // rows (17, not the 18 of the bank model), which brings the workgroup's
+    // LDS under 80 KB, so two of them share a CU (2.1 -> 3.0 TB/s at E = 65536)
+    constexpr int P = bp10t_row(NQ, sizeof(TC));
     constexpr int SA = NQ * P;                   // slab of A: [j][i]
     constexpr int SB = NG * P;                   // slab of B: [b][i]
     constexpr int W = geo_vec(NG, sizeof(TG));   // interleave of the geometric layout
@@ -78,6 +81,14 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     // measured at E = 262144: Nq = 12 is faster with LDS tables in FP32
     // arithmetic only.
     constexpr bool TLDS = NQ > 12 || (NQ == 12 && sizeof(TC) == 4);
+    // FP64 from Nq = 11: an empty asm with a memory clobber between line
+    // products that share a table (the r-direction's interpolation and
+    // projection; from Nq = 14 also the lines of consecutive passes) makes each
+    // read the table again instead of the compiler holding the first one's
+    // values in registers for the next (measured at E = 65536: Nq = 11 3.3 ->
+    // 3.9, Nq = 12 3.2 -> 3.6, Nq = 14 2.5 -> 3.0, Nq = 15 2.4 -> 3.0 TB/s).
+    constexpr bool FENCE_R = sizeof(TC) == 8 && NQ >= 11;
+    constexpr bool FENCE_S = sizeof(TC) == 8 && NQ >= 14;
     constexpr int IOR = GE > 0 ? GE : 1, IOC = QE > 0 ? QE : 1;
     __shared__ TC sIe[TLDS ? HG : 1][HQ];
     __shared__ TC sIo[TLDS ? IOR : 1][IOC];
@@ -187,6 +198,7 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
             TC x[NQ], z[NG];
 #pragma unroll
             for (int m = 0; m < NQ; ++m) x[m] = sA[c * SA + m * P + i];
+            if constexpr (FENCE_S) asm volatile("" ::: "memory");
             line_interp<NQ>(x, z, Ie, Io);
 #pragma unroll
             for (int b = 0; b < NG; ++b) sB[c * SB + b * P + i] = z[b];
@@ -216,9 +228,11 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
                 TC *row = sB + c * SB + b * P;
 #pragma unroll
                 for (int m = 0; m < NQ; ++m) x[m] = row[m];
+                if constexpr (FENCE_R) asm volatile("" ::: "memory");
                 line_interp<NQ>(x, z, Ie, Io);
 #pragma unroll
                 for (int a = 0; a < NG; ++a) z[a] *= to_compute(sw[geo_offset(a + NG * b, c, NG, W)], TC{});
+                if constexpr (FENCE_R) asm volatile("" ::: "memory");
                 line_project<NQ>(z, w, Ie, Io);
 #pragma unroll
                 for (int m = 0; m < NQ; ++m) row[m] = w[m];
@@ -245,6 +259,7 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
             TC v[NG], w[NQ];
 #pragma unroll
             for (int b = 0; b < NG; ++b) v[b] = sB[c * SB + b * P + i];
+            if constexpr (FENCE_S) asm volatile("" ::: "memory");
             line_project<NQ>(v, w, Ie, Io);
 #pragma unroll
             for (int j = 0; j < NQ; ++j) sA[c * SA + j * P + i] = w[j];

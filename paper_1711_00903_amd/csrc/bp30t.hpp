@@ -72,10 +72,13 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     const int li = L % NQ, lj = L / NQ;
     // Half tables: in registers for small Nq, in LDS beyond (the lines then
     // need the registers); the LDS copies are fetched ahead of the element's
-    // loads and stored once those are issued.  The crossover was measured at
-    // E = 262144: LDS from Nq = 11 (Nq = 12 in FP64 arithmetic stays faster
-    // with registers).
-    constexpr bool TLDS = NQ > 12 || NQ == 11 || (NQ == 12 && sizeof(TC) == 4);
+    // loads and stored once those are issued.  Measured crossovers: FP32
+    // arithmetic from Nq = 11; FP64 arithmetic from Nq = 10, together with one
+    // slab of factors ahead and the table reads of consecutive line products
+    // kept apart (FENCE, below), which fit the kernel in two waves per SIMD
+    // (Nq = 10: 3.9 -> 4.5 TB/s, Nq = 12: 3.0 -> 4.1 TB/s at E = 65536).
+    constexpr bool FENCE = sizeof(TC) == 8 && NQ >= 10;
+    constexpr bool TLDS = FENCE || NQ > 12 || NQ == 11 || (NQ == 12 && sizeof(TC) == 4);
     constexpr int QEC = QE > 0 ? QE : 1;
     __shared__ TC sIe[TLDS ? HG : 1][HQ];
     __shared__ TC sIo[TLDS ? GE : 1][QEC];
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     // the metric step (all of them no longer fit in registers).  The factors
     // stay in their stored type until the metric step: a widening right after
     // the load would wait for every request before the first barrier.
-    constexpr int GPRE = NG <= 9 ? NG : (NG <= 11 ? 4 : (NG <= 16 ? 3 : 2));
+    constexpr int GPRE = FENCE ? 1 : (NG <= 9 ? NG : (NG <= 11 ? 4 : (NG <= 16 ? 3 : 2)));
     TG g[6][NG];
     const int64_t gb = e * (6 * NPG);
     const int gcol = col ? L : 0;
@@ -172,6 +175,11 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
         line_deriv<NG>(x, z, Dp, Dm);
 #pragma unroll
         for (int a = 0; a < NG; ++a) V0[c * S + p * P + a] = z[a];
+        // An empty asm with a memory clobber between two line products makes
+        // the second read its LDS half tables again: otherwise the compiler
+        // keeps the first product's table values live in registers for the
+        // second (at Ng = 16 that alone pushed the kernel to one wave per SIMD).
+        if constexpr (FENCE) asm volatile("" ::: "memory");
 #pragma unroll
         for (int m = 0; m < NG; ++m) x[m] = V2[c * S + m * P + p];   // column (a = p)
         line_deriv<NG>(x, z, Dp, Dm);
@@ -187,8 +195,12 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
 #pragma unroll
         for (int c = 0; c < NG; ++c) ut[c] = V2[c * S + o];
         line_deriv<NG>(ut, qt, Dp, Dm);
+        if constexpr (FENCE) asm volatile("" ::: "memory");
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
+            // one slab at a time: without the barrier the scheduler hoists the
+            // later slabs' loads and LDS reads and holds them all in registers
+            if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
             if (c + GPRE < NG) gload(c + GPRE);
             const TC qr = V0[c * S + o], qs = V1[c * S + o];
             const TC grr = to_compute(g[0][c], TC{}), grs = to_compute(g[1][c], TC{}),
@@ -198,6 +210,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
             V1[c * S + o] = grs * qr + gss * qs + gst * qt[c];
             wt[c] = grt * qr + gst * qs + gtt * qt[c];
         }
+        if constexpr (FENCE) asm volatile("" ::: "memory");
         line_deriv_t<NG>(wt, vt, Dp, Dm);
         if (lambda != TC(0)) {
             // u~ is read again from this lane's own column of V2 instead of
@@ -281,6 +294,12 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     }
 }
 
+}  // namespace fem
+
+#include "bp30t2.hpp"
+
+namespace fem {
+
 template <int NQ, class TG, class TV>
 hipError_t bp30t_launch_t(const ApplyArgs &a, hipStream_t s)
 {
@@ -294,10 +313,16 @@ hipError_t bp30t_launch_t(const ApplyArgs &a, hipStream_t s)
     if (chunk > max_grid(bp30t_threads(NQ))) chunk = max_grid(bp30t_threads(NQ));
     for (int64_t e0 = 0; e0 < a.E; e0 += chunk) {
         const unsigned grid = static_cast<unsigned>(a.E - e0 < chunk ? a.E - e0 : chunk);
-        hipLaunchKernelGGL((bp30t_kernel<NQ, TG, TV>), dim3(grid), dim3(bp30t_threads(NQ)), 0, s, a.E, a.I1d,
-                           a.Dgl, static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
-                           static_cast<TC>(a.lambda), static_cast<const TV *>(a.u), static_cast<TY *>(a.y),
-                           static_cast<TC>(a.beta), oscale, e0);
+        if constexpr (bp30t_two_volumes(NQ, sizeof(TC)))
+            hipLaunchKernelGGL((bp30t2_kernel<NQ, TG, TV>), dim3(grid), dim3(bp30t_threads(NQ)), 0, s, a.E, a.I1d,
+                               a.Dgl, static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
+                               static_cast<TC>(a.lambda), static_cast<const TV *>(a.u), static_cast<TY *>(a.y),
+                               static_cast<TC>(a.beta), oscale, e0);
+        else
+            hipLaunchKernelGGL((bp30t_kernel<NQ, TG, TV>), dim3(grid), dim3(bp30t_threads(NQ)), 0, s, a.E, a.I1d,
+                               a.Dgl, static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
+                               static_cast<TC>(a.lambda), static_cast<const TV *>(a.u), static_cast<TY *>(a.y),
+                               static_cast<TC>(a.beta), oscale, e0);
     }
     return hipGetLastError();
 }

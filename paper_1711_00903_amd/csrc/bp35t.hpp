@@ -56,6 +56,12 @@ __attribute__((amdgpu_waves_per_eu(bp35t_min_waves(NQ)))) void bp35t_kernel(
     // beyond Nq = 11, where three no longer fit in registers)
     constexpr int GPRE = NV < 3 ? NV : (sizeof(TC) == 8 && NQ >= 12 ? 2 : 3);
     static_assert(NQ >= 2 && NC <= bp35t_threads(NQ), "one lane per GLL column");
+    // FP64 from Nq = 12: an empty asm with a memory clobber between two line
+    // products makes the second read its LDS half tables again; otherwise the
+    // compiler holds the first product's table values in registers for the
+    // second, which cost a wave per SIMD (measured at E = 65536: Nq = 12 4.0 ->
+    // 5.1, Nq = 14 2.6 -> 5.1, Nq = 16 3.3 -> 5.7 TB/s).
+    constexpr bool FENCE = sizeof(TC) == 8 && NQ >= 12;
 
     __shared__ __align__(16) TC V0[VOL];
     __shared__ __align__(16) TC V1[VOL];
@@ -126,6 +132,7 @@ __attribute__((amdgpu_waves_per_eu(bp35t_min_waves(NQ)))) void bp35t_kernel(
         const int o = cj * P + ci;
         TC qt[NQ], wt[NQ];
         line_deriv<NQ>(uc, qt, Dp, Dm);
+        if constexpr (FENCE) asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {
             if (k % W == 0 && k / W + GPRE < NV) {
@@ -143,6 +150,7 @@ __attribute__((amdgpu_waves_per_eu(bp35t_min_waves(NQ)))) void bp35t_kernel(
             V0[k * S + o] = grs * qr + gss * qs + gst * qt[k];
             wt[k] = grt * qr + gst * qs + gtt * qt[k];
         }
+        if constexpr (FENCE) asm volatile("" ::: "memory");
         line_deriv_t<NQ>(wt, vt, Dp, Dm);
         if (lambda != TC(0)) {
             // u is fetched again (from cache) rather than kept live through the
@@ -168,6 +176,7 @@ __attribute__((amdgpu_waves_per_eu(bp35t_min_waves(NQ)))) void bp35t_kernel(
         line_deriv_t<NQ>(v, w, Dp, Dm);
 #pragma unroll
         for (int b = 0; b < NQ; ++b) V0[lk * S + b * P + lp] = w[b];
+        if constexpr (FENCE) asm volatile("" ::: "memory");
 #pragma unroll
         for (int a = 0; a < NQ; ++a) v[a] = V1[lk * S + lp * P + a];
         line_deriv_t<NQ>(v, w, Dp, Dm);

@@ -43,10 +43,15 @@ constexpr int interp_half_values(int nq)
     return ((ng + 1) / 2) * ((nq + 1) / 2) + (ng / 2) * (nq / 2 > 0 ? nq / 2 : 1);
 }
 
+// Row length of the line-per-lane BP1.0 kernel's LDS volumes: the bank
+// model's, except FP64 at Nq = 16, where odd rows keep the workgroup under
+// 80 KB of LDS (two workgroups per CU).
+constexpr int bp10t_row(int nq, int bytes) { return bytes == 8 && nq == 16 ? 17 : lds_row(nq, bytes); }
+
 constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 {
     const int ng = nq + 1;
-    const int p = lds_row(nq, bytes);
+    const int p = bp10t_row(nq, bytes);
     const int av = ng * nq * p;                                       // [c][j][i] volume
     const int wv = (ng * ng * ng * gbytes + 8 + bytes - 1) / bytes;   // staged scaled Jacobians
     const int tab = nq >= 12 ? interp_half_values(nq) : 0;   // LDS tables (an upper bound at Nq = 12)
@@ -54,14 +59,20 @@ constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 }
 
 // BP3.0 with one element per workgroup runs the line-per-lane kernel
-// (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes.
+// (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes -- or two
+// (bp30t2.hpp) in FP64 arithmetic at Nq = 11 and from Nq = 13, where the third
+// volume kept a second workgroup off the CU (measured at E = 65536: Nq = 11
+// 2.6 -> 4.1, Nq = 13 2.7 -> 4.2, Nq = 14 2.8 -> 4.1, Nq = 15 3.4 -> 4.4,
+// Nq = 16 1.5 -> 3.0 TB/s).
 constexpr bool bp30_line(int nq, int epb) { return epb == 1; }
+constexpr bool bp30t_two_volumes(int nq, int bytes) { return bytes == 8 && (nq == 11 || nq >= 13); }
 
 constexpr int bp30t_lds_bytes(int nq, int bytes)
 {
     const int ng = nq + 1;
-    const int tab = nq >= 11 ? interp_half_values(nq) + 2 * ((ng + 1) / 2) * (ng / 2) : 0;   // LDS tables
-    return (3 * ng * ng * lds_row(ng, bytes) + tab) * bytes;
+    const bool tlds = nq >= 11 || (bytes == 8 && nq >= 10);
+    const int tab = tlds ? interp_half_values(nq) + 2 * ((ng + 1) / 2) * (ng / 2) : 0;   // LDS tables
+    return ((bp30t_two_volumes(nq, bytes) ? 2 : 3) * ng * ng * lds_row(ng, bytes) + tab) * bytes;
 }
 
 // BP3.5 with one element per workgroup and Nq >= 11 runs the line-per-lane

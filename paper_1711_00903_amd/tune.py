@@ -1,9 +1,12 @@
 """Autotuner of the element kernels' launch shape.
 
 For each (operator, degree, precision) it times every supported number of
-elements per workgroup on a device-resident mesh, keeps the fastest, and
-writes the result as a tune table that ``fem_tune_load`` reads ("op N prec epb
-grid_cap" per line).  The measured throughputs double as the roofline sweep
+elements per workgroup -- and, for the column kernels, which loop over element
+groups, every persistent grid size of GRID_CAPS -- on a device-resident mesh,
+keeps the fastest, and writes the result as a tune table that ``fem_tune_load``
+reads ("op N prec epb grid_cap" per line).  The line-per-lane kernels have one
+launch shape each; their LDS layout and table placement per (operator, degree,
+arithmetic) were chosen by measurement and are fixed in the kernels.  The measured throughputs double as the roofline sweep
 over N (GB/s of algorithmic traffic per apply).
 """
 from __future__ import annotations
@@ -44,16 +47,19 @@ def alg_flops(op: str, N: int, E: int) -> int:
 _F64_FIELDS = (fem.FEM_F64, fem.FEM_F32G64, fem.FEM_BF16G64, fem.FEM_F16G64)
 
 
-def kernel_family(op: str, N: int, epb: int) -> str:
+def kernel_family(op: str, N: int, epb: int, prec: int = fem.FEM_F64) -> str:
     """The kernel an apply runs with `epb` elements per workgroup (the
     library's dispatch): line-per-lane kernels with one element per
     workgroup (BP1.0, BP3.0 at every degree, BP3.5 from Nq = 11), the column
-    kernels otherwise."""
+    kernels otherwise; BP3.0 in FP64 arithmetic at Nq = 11 and from Nq = 13
+    runs the two-volume line kernel."""
     if op == "BP10":
         return "bp10t" if epb == 1 else "bp10"
     if op == "BP35":
         return "bp35t" if epb == 1 and N + 1 >= 11 else "bp35"
-    return "bp30t" if epb == 1 else "bp30"
+    if epb != 1:
+        return "bp30"
+    return "bp30t2" if prec in _F64_FIELDS and (N + 1 == 11 or N + 1 >= 13) else "bp30t"
 
 
 def lds_values(family: str, N: int) -> tuple[int, int]:
@@ -78,6 +84,10 @@ def lds_values(family: str, N: int) -> tuple[int, int]:
       t-work on the Gauss grid (two derivatives out, metric step, two
       transposes, the r-transpose reading three volumes): 2 g q^2 + 2 g^2 q
       + 9 g^3 reads, 2 g q^2 + 2 g^2 q + 7 g^3 writes.
+    * bp30t2 (the same with two volumes): u~ and its r-derivative written
+      together, the metric lane's u~ column read once, the s-derivative in
+      place, the t-term added to the s-term once: 2 g q^2 + 2 g^2 q + 8 g^3
+      reads, 2 g q^2 + 2 g^2 q + 7 g^3 writes.
     * bp30 (lane per Gauss column): whole-line reads per output in the r- and
       s-interpolation and projection (2 g q^3 + 2 g^2 q^2) and in the
       gradient and its transpose (4 g^4); q^3 + 2 g q^2 + g^2 q + 3 g^3 writes.
@@ -94,6 +104,8 @@ def lds_values(family: str, N: int) -> tuple[int, int]:
         return 2 * g * q ** 3 + 2 * g * g * q * q, q ** 3 + 2 * g * q * q + g * g * q
     if family == "bp30t":
         return 2 * g * q * q + 2 * g * g * q + 9 * g ** 3, 2 * g * q * q + 2 * g * g * q + 7 * g ** 3
+    if family == "bp30t2":
+        return 2 * g * q * q + 2 * g * g * q + 8 * g ** 3, 2 * g * q * q + 2 * g * g * q + 7 * g ** 3
     if family == "bp30":
         return 2 * g * q ** 3 + 2 * g * g * q * q + 4 * g ** 4, q ** 3 + 2 * g * q * q + g * g * q + 3 * g ** 3
     raise ValueError(family)
@@ -102,7 +114,7 @@ def lds_values(family: str, N: int) -> tuple[int, int]:
 def lds_bytes(op: str, N: int, E: int, prec: int, epb: int) -> int:
     """LDS bytes (read + written) of one apply: values of the compute type
     (FP64 with FP64 fields, FP32 otherwise)."""
-    r, w = lds_values(kernel_family(op, N, epb), N)
+    r, w = lds_values(kernel_family(op, N, epb, prec), N)
     return E * (r + w) * (8 if prec in _F64_FIELDS else 4)
 
 
@@ -119,10 +131,17 @@ def _time(fn, reps: int, stream) -> float:
     return s.elapsed_time(e) / reps
 
 
+# persistent grid sizes tried for the column kernels: 4, 8 and 16 workgroups
+# per CU of the 256, and uncapped (one workgroup per element group)
+GRID_CAPS = (0, 1024, 2048, 4096)
+
+
 def autotune(X: np.ndarray, ops=("BP10", "BP35", "BP30"), Ns=range(1, 16), precs=(fem.FEM_F64,),
-             reps: int = 10, h: float | None = None, log=None, seed: int = 0) -> list[dict]:
-    """Time every supported packing of each (op, N, prec) on the mesh X; returns
-    one record per configuration with the fastest packing first-class."""
+             reps: int = 10, h: float | None = None, log=None, seed: int = 0,
+             grid_caps=GRID_CAPS) -> list[dict]:
+    """Time every supported packing of each (op, N, prec) on the mesh X, and
+    for the column kernels every persistent grid size of `grid_caps`; returns
+    one record per configuration with the fastest (packing, grid cap)."""
     stream = torch.cuda.current_stream()
     gen = torch.Generator(device="cuda")
     out = []
@@ -143,20 +162,29 @@ def autotune(X: np.ndarray, ops=("BP10", "BP35", "BP30"), Ns=range(1, 16), precs
                 timings = {}
                 try:
                     for epb in fem.fem_supported_epb(opid, N, prec):
-                        fem.fem_tune_set(opid, N, prec, epb, 0)
-                        timings[epb] = _time(call, reps, stream)
+                        # the column kernels loop over element groups, so a
+                        # capped grid makes them persistent; the line kernels
+                        # only split their launch, so they run uncapped
+                        caps = grid_caps if kernel_family(op, N, epb, prec) in ("bp10", "bp35", "bp30") else (0,)
+                        for cap in caps:
+                            fem.fem_tune_set(opid, N, prec, epb, cap)
+                            timings[(epb, cap)] = _time(call, reps, stream)
                 finally:
                     fem.fem_tune_set(opid, N, prec, 0, 0)
-                best = min(timings, key=timings.get)
-                ms = timings[best]
+                (best, best_cap) = min(timings, key=timings.get)
+                ms = timings[(best, best_cap)]
+                # a cap is kept only where it beats the uncapped grid of the
+                # same packing by more than 2%
+                if best_cap and timings[(best, 0)] <= 1.02 * ms:
+                    best_cap, ms = 0, timings[(best, 0)]
                 nbytes = alg_bytes(op, N, E, prec)
-                rec = dict(op=op, N=N, prec=prec, E=E, epb=best, grid_cap=0, ms=ms,
+                rec = dict(op=op, N=N, prec=prec, E=E, epb=best, grid_cap=best_cap, ms=ms,
                            gbs=nbytes / (ms * 1e-3) / 1e9, gdofs=E * dev.np / (ms * 1e-3) / 1e9,
                            tflops=alg_flops(op, N, E) / (ms * 1e-3) / 1e12,
-                           all_ms={int(k): v for k, v in timings.items()})
+                           all_ms={f"{k[0]}/{k[1]}": v for k, v in timings.items()})
                 out.append(rec)
                 if log:
-                    log(f"tune {op} N={N} prec={prec}: epb {best} {ms:.4f} ms {rec['gbs']:.0f} GB/s "
+                    log(f"tune {op} N={N} prec={prec}: epb {best} cap {best_cap} {ms:.4f} ms {rec['gbs']:.0f} GB/s "
                         f"{rec['gdofs']:.1f} GDOF/s  all {rec['all_ms']}")
             del u, y
         dev.drop_geometry()
