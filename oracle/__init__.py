@@ -62,6 +62,7 @@ def lib() -> C.CDLL:
     L.ora_bp35.argtypes = [C.c_int, i64, _dp, _dp, _dp, C.c_double, _dp, _dp, C.c_int]
     L.ora_bp30.argtypes = [C.c_int, i64, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, C.c_int]
     L.ora_set_threads.argtypes = [C.c_int]
+    L.ora_cg_residual_ld.argtypes = [C.c_int, i64, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp]
     L.ora_set_threads.restype = C.c_int
     return L
 
@@ -231,6 +232,21 @@ class Problem:
 
     def stiff30(self, u, lam=0.0):
         return bp30(self.N, self.G_gl(), u, self.wJ_gl() if lam else None, lam)
+
+    def cg_residual_ld(self, x, b, lam=1.0) -> tuple[float, float]:
+        """(||b - (S + lam M) x||^2, ||b||^2) with every operation in long double
+        (fem_oracle.c: ora_cg_residual_ld)."""
+        T = tables(self.N)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        E = x.shape[0]
+        out = np.zeros(2)
+        wJ = self.wJ_gl() if lam else np.zeros(1)
+        st = lib().ora_cg_residual_ld(self.N, E, _p(np.ascontiguousarray(T.I)), _p(np.ascontiguousarray(T.D)),
+                                      _p(self.G_gll()), _p(wJ), float(lam), _p(x), _p(b), _p(out))
+        if st:
+            raise ValueError("ora_cg_residual_ld: bad arguments")
+        return float(out[0]), float(out[1])
 
     def cg_operator(self, u, lam=1.0):
         """A u = S3.5 u + lam * M1.0 u (the operator of the CG workload)."""

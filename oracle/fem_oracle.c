@@ -511,6 +511,144 @@ int ora_bp30(int N, int64_t E, const double *I1d, const double *Dgl, const doubl
     return 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * The residual of the CG workload in extended precision.
+ *
+ * ||b - (S + lambda M) x||^2 and ||b||^2 over E elements, with S the BP3.5
+ * stiffness (Alg. 4, eq. stiffQuad) and M the BP1.0 mass (Alg. 3, eq.
+ * massQuad), every product and sum taken in long double (64-bit significand
+ * on x86-64) on the FP64 inputs as stored.  Near the rounding floor of the
+ * CG workload an FP64 evaluation of b - Ax carries rounding of the size of the
+ * residual itself; this one measures the residual of the stored x.
+ * The contractions are those of interpolate / project / stiffness_collocated
+ * above, in the same order.
+ * ------------------------------------------------------------------------- */
+typedef long double ora_ld;
+
+static void interpolate_ld(int nq, int ng, const double *I, const ora_ld *q, ora_ld *t1, ora_ld *t2,
+                           ora_ld *out)
+{
+    for (int c = 0; c < nq; ++c)
+        for (int j = 0; j < ng; ++j)
+            for (int a = 0; a < nq; ++a) {
+                ora_ld s = 0.0L;
+                for (int b = 0; b < nq; ++b) s += (ora_ld)I[j * nq + b] * q[(c * nq + b) * nq + a];
+                t1[(c * ng + j) * nq + a] = s;
+            }
+    for (int c = 0; c < nq; ++c)
+        for (int j = 0; j < ng; ++j)
+            for (int i = 0; i < ng; ++i) {
+                ora_ld s = 0.0L;
+                for (int a = 0; a < nq; ++a) s += (ora_ld)I[i * nq + a] * t1[(c * ng + j) * nq + a];
+                t2[(c * ng + j) * ng + i] = s;
+            }
+    for (int k = 0; k < ng; ++k)
+        for (int j = 0; j < ng; ++j)
+            for (int i = 0; i < ng; ++i) {
+                ora_ld s = 0.0L;
+                for (int c = 0; c < nq; ++c) s += (ora_ld)I[k * nq + c] * t2[(c * ng + j) * ng + i];
+                out[(k * ng + j) * ng + i] = s;
+            }
+}
+
+static void project_ld(int nq, int ng, const double *I, const ora_ld *qt, ora_ld *t1, ora_ld *t2, ora_ld *out)
+{
+    for (int k = 0; k < ng; ++k)
+        for (int b = 0; b < nq; ++b)
+            for (int i = 0; i < ng; ++i) {
+                ora_ld s = 0.0L;
+                for (int j = 0; j < ng; ++j) s += (ora_ld)I[j * nq + b] * qt[(k * ng + j) * ng + i];
+                t1[(k * nq + b) * ng + i] = s;
+            }
+    for (int k = 0; k < ng; ++k)
+        for (int b = 0; b < nq; ++b)
+            for (int a = 0; a < nq; ++a) {
+                ora_ld s = 0.0L;
+                for (int i = 0; i < ng; ++i) s += (ora_ld)I[i * nq + a] * t1[(k * nq + b) * ng + i];
+                t2[(k * nq + b) * nq + a] = s;
+            }
+    for (int c = 0; c < nq; ++c)
+        for (int b = 0; b < nq; ++b)
+            for (int a = 0; a < nq; ++a) {
+                ora_ld s = 0.0L;
+                for (int k = 0; k < ng; ++k) s += (ora_ld)I[k * nq + c] * t2[(k * nq + b) * nq + a];
+                out[(c * nq + b) * nq + a] = s;
+            }
+}
+
+static void stiffness_ld(int n, const double *D, const double *G, const ora_ld *q, ora_ld *rqr, ora_ld *rqs,
+                         ora_ld *rqt, ora_ld *out)
+{
+    const int64_t np = (int64_t)n * n * n;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int64_t id = (k * n + j) * n + i;
+                ora_ld qr = 0.0L, qs = 0.0L, qt = 0.0L;
+                for (int m = 0; m < n; ++m) {
+                    qr += (ora_ld)D[i * n + m] * q[(k * n + j) * n + m];
+                    qs += (ora_ld)D[j * n + m] * q[(k * n + m) * n + i];
+                    qt += (ora_ld)D[k * n + m] * q[(m * n + j) * n + i];
+                }
+                ora_ld grr = G[0 * np + id], grs = G[1 * np + id], grt = G[2 * np + id];
+                ora_ld gss = G[3 * np + id], gst = G[4 * np + id], gtt = G[5 * np + id];
+                rqr[id] = grr * qr + grs * qs + grt * qt;
+                rqs[id] = grs * qr + gss * qs + gst * qt;
+                rqt[id] = grt * qr + gst * qs + gtt * qt;
+            }
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int64_t id = (k * n + j) * n + i;
+                ora_ld s = 0.0L;
+                for (int m = 0; m < n; ++m) {
+                    s += (ora_ld)D[m * n + i] * rqr[(k * n + j) * n + m];
+                    s += (ora_ld)D[m * n + j] * rqs[(k * n + m) * n + i];
+                    s += (ora_ld)D[m * n + k] * rqt[(m * n + j) * n + i];
+                }
+                out[id] = s;
+            }
+}
+
+/* Returns 0 and writes rr_bb[0] = ||b - A x||^2, rr_bb[1] = ||b||^2.
+ * G: BP3.5 factors [E][6][nq^3]; wJ: BP1.0 scaled Jacobians at GL nodes
+ * [E][ng^3] (unused when lambda == 0). */
+int ora_cg_residual_ld(int N, int64_t E, const double *I1d, const double *D1d, const double *G,
+                       const double *wJ, double lambda, const double *x, const double *b, double *rr_bb)
+{
+    if (N < 1 || N > ORA_MAXN || E < 0 || (lambda != 0.0 && !wJ)) return 1;
+    const int nq = N + 1, ng = N + 2;
+    const int64_t np = (int64_t)nq * nq * nq, npg = (int64_t)ng * ng * ng;
+    ora_ld rr = 0.0L, bb = 0.0L;
+#pragma omp parallel reduction(+ : rr, bb)
+    {
+        ora_ld *buf = (ora_ld *)malloc(sizeof(ora_ld) * (4 * npg + 6 * np));
+        ora_ld *t1 = buf, *t2 = buf + npg, *qg = buf + 2 * npg, *mg = buf + 3 * npg;
+        ora_ld *q = buf + 4 * npg, *rqr = q + np, *rqs = q + 2 * np, *rqt = q + 3 * np, *ys = q + 4 * np;
+        ora_ld *xm = q + 5 * np;
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < E; ++e) {
+            for (int64_t n = 0; n < np; ++n) q[n] = x[e * np + n];
+            stiffness_ld(nq, D1d, G + 6 * np * e, q, rqr, rqs, rqt, ys);
+            if (lambda != 0.0) {
+                interpolate_ld(nq, ng, I1d, q, t1, t2, qg);
+                for (int64_t n = 0; n < npg; ++n) mg[n] = qg[n] * (ora_ld)wJ[e * npg + n];
+                project_ld(nq, ng, I1d, mg, t1, t2, xm);
+            }
+            for (int64_t n = 0; n < np; ++n) {
+                ora_ld ax = ys[n] + (lambda != 0.0 ? (ora_ld)lambda * xm[n] : 0.0L);
+                ora_ld r = (ora_ld)b[e * np + n] - ax;
+                rr += r * r;
+                bb += (ora_ld)b[e * np + n] * b[e * np + n];
+            }
+        }
+        free(buf);
+    }
+    rr_bb[0] = (double)rr;
+    rr_bb[1] = (double)bb;
+    return 0;
+}
+
 int ora_set_threads(int n)
 {
 #ifdef _OPENMP
