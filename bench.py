@@ -11,8 +11,9 @@ host's cores on a bounded sample of the same workload.
 
 The record also carries two sub-records measured in the same run: ``small_case``
 (BP1.0, N = 3, E = 512: cache-resident, time per apply) and ``cg`` (CG on
-S + 4096 M at N = 7 on the 64^3 mesh to relative residual 1e-10, FP64 against
-BF16-stored geometric data, three solves each).
+S + 4096 M at N = 7 on the 64^3 mesh to relative residual 1e-10: FP64 against
+BF16-stored geometric data with FP64 vectors, and against iterative refinement
+with an FP32 inner CG on BF16-stored geometric data; three solves each).
 
 ``--workload`` selects another single-operator workload with the same record
 (BP1.0 or BP3.0, N = 7, on the 64^3 mesh); ``--cg``, ``--sweep`` and
@@ -823,7 +824,7 @@ def main() -> int:
         dev.drop_geometry()
         del dev
         torch.cuda.empty_cache()
-        cg = cg_arms(64, 4096.0, 1e-10, ["fp64", "bf16g64"], solves=3)
+        cg = cg_arms(64, 4096.0, 1e-10, ["fp64", "bf16g64", "bf16g_ir"], solves=3)
         log(f"bench: cg {json.dumps(cg)}")
 
     cpu = None

@@ -76,19 +76,18 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     const int64_t e = e0 + blockIdx.x;
 
     // half tables, uniform across the wave: in registers for small Nq, in LDS
-    // beyond (the lines then need the registers); the LDS copy is fetched
-    // before the element's loads and stored after they are issued.  Crossover
-    // measured at E = 262144: Nq = 12 is faster with LDS tables in FP32
-    // arithmetic only.
-    constexpr bool TLDS = NQ > 12 || (NQ == 12 && sizeof(TC) == 4);
+    // from Nq = 12 (the lines then need the registers); the LDS copy is
+    // fetched before the element's loads and stored after they are issued.
+    constexpr bool TLDS = NQ >= 12;
     // FP64 from Nq = 11: an empty asm with a memory clobber between line
     // products that share a table (the r-direction's interpolation and
-    // projection; from Nq = 14 also the lines of consecutive passes) makes each
+    // projection; from Nq = 13 also the lines of consecutive passes) makes each
     // read the table again instead of the compiler holding the first one's
     // values in registers for the next (measured at E = 65536: Nq = 11 3.3 ->
-    // 3.9, Nq = 12 3.2 -> 3.6, Nq = 14 2.5 -> 3.0, Nq = 15 2.4 -> 3.0 TB/s).
+    // 3.9, Nq = 12 3.2 -> 3.7 (with the tables in LDS), Nq = 13 2.8 -> 3.1,
+    // Nq = 14 2.5 -> 3.0, Nq = 15 2.4 -> 3.0 TB/s).
     constexpr bool FENCE_R = sizeof(TC) == 8 && NQ >= 11;
-    constexpr bool FENCE_S = sizeof(TC) == 8 && NQ >= 14;
+    constexpr bool FENCE_S = sizeof(TC) == 8 && NQ >= 12;
     constexpr int IOR = GE > 0 ? GE : 1, IOC = QE > 0 ? QE : 1;
     __shared__ TC sIe[TLDS ? HG : 1][HQ];
     __shared__ TC sIo[TLDS ? IOR : 1][IOC];

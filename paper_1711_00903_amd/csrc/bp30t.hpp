@@ -64,8 +64,8 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     const int ca = L % NG, cb = L / NG;
 
     // the u column of lane (i,j) and the 6 Ng factors of Gauss column (ca,cb).
-    // Every lane loads (lanes beyond the columns re-read column 0 and never use
-    // it): under a lane condition the compiler widens a narrow value inside the
+    // Every lane loads (lanes beyond the columns re-read another column and never
+    // use it): under a lane condition the compiler widens a narrow value inside the
     // branch and waits for it there, one load at a time.  The u column is
     // requested first and waited for only after the factor requests are out.
     const bool gll = L < NC;
@@ -105,7 +105,11 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     constexpr int GPRE = FENCE ? 1 : (NG <= 9 ? NG : (NG <= 11 ? 4 : (NG <= 16 ? 3 : 2)));
     TG g[6][NG];
     const int64_t gb = e * (6 * NPG);
-    const int gcol = col ? L : 0;
+    // a lane without a column re-reads the first column of its own wave (every
+    // wave holds at least one column), so the wave's requests touch no line
+    // outside its own columns: with non-temporal loads a re-read of column 0
+    // from another wave went to HBM again (+17% of the bytes with BF16 factors)
+    const int gcol = col ? L : (L & ~(kWave - 1));
     auto gload = [&](int c) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) g[f][c] = nt_load(G + gb + f * NPG + geo_offset(gcol, c, NG, W));

@@ -32,11 +32,12 @@
 
 namespace fem {
 
-// Slabs of factors requested ahead of their use in the metric step: two; at
-// Ng = 17 one, with three waves per SIMD asked of the register allocator (two
-// workgroups of five waves per CU) at the cost of 36 bytes of spill per lane.
+// Slabs of factors requested ahead of their use in the metric step: two; one
+// at Ng = 17.  There, asking the register allocator for three waves per SIMD
+// (two five-wave workgroups per CU) measured 2% faster but spilled 120 bytes
+// per lane, which went to HBM as scratch traffic; the kernel runs without.
 constexpr int bp30t2_gpre(int nq) { return nq >= 16 ? 1 : 2; }
-constexpr int bp30t2_min_waves(int nq) { return nq >= 16 ? 3 : 1; }
+constexpr int bp30t2_min_waves(int nq) { return 1; }
 
 template <int NQ, class TG, class TV>
 __global__ __launch_bounds__(bp30t_threads(NQ))
@@ -78,7 +79,7 @@ __attribute__((amdgpu_waves_per_eu(bp30t2_min_waves(NQ)))) void bp30t2_kernel(
 
     // requests, oldest first: the lane's table entries, its u column, the
     // first GPRE slabs of its Gauss column's factors (every lane issues them;
-    // lanes without a column re-read column 0 and never use it)
+    // lanes without a column re-read another column and never use it)
     double ti0, ti1, td0, td1;
     interp_pair_load<NQ>(I1d, L, ti0, ti1);
     deriv_pair_load<NG>(Dgl, L, td0, td1);
@@ -92,7 +93,7 @@ __attribute__((amdgpu_waves_per_eu(bp30t2_min_waves(NQ)))) void bp30t2_kernel(
     __builtin_amdgcn_sched_barrier(0);
     TG g[6][NG];
     const int64_t gb = e * (6 * NPG);
-    const int gcol = col ? L : 0;
+    const int gcol = col ? L : (L & ~(kWave - 1));   // as in bp30t_kernel
     auto gload = [&](int c) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) g[f][c] = nt_load(G + gb + f * NPG + geo_offset(gcol, c, NG, W));

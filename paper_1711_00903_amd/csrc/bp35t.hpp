@@ -71,7 +71,10 @@ __attribute__((amdgpu_waves_per_eu(bp35t_min_waves(NQ)))) void bp35t_kernel(
     const int L = threadIdx.x;
     const int64_t e = e0 + blockIdx.x;
     const bool own = L < NC;                     // owns column (ci,cj) and lines (lp, lk)
-    const int gcol = own ? L : 0;                // lanes beyond re-read column 0 and never store
+    // lanes beyond the columns re-read the first column of their own wave (every
+    // wave holds at least one) and never store: no request of a wave touches a
+    // line outside its own columns
+    const int gcol = own ? L : (L & ~(kWave - 1));
     const int ci = gcol % NQ, cj = gcol / NQ;
     const int lp = ci, lk = cj;
 

@@ -54,7 +54,7 @@ constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
     const int p = bp10t_row(nq, bytes);
     const int av = ng * nq * p;                                       // [c][j][i] volume
     const int wv = (ng * ng * ng * gbytes + 8 + bytes - 1) / bytes;   // staged scaled Jacobians
-    const int tab = nq >= 12 ? interp_half_values(nq) : 0;   // LDS tables (an upper bound at Nq = 12)
+    const int tab = nq >= 12 ? interp_half_values(nq) : 0;   // LDS tables
     return ((av > wv ? av : wv) + ng * ng * p + tab) * bytes;
 }
 
