@@ -121,9 +121,12 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
             upc[q] = t < NP / 8 ? src[t] : R16{};
         }
     } else {
+        // every lane loads (lanes without a column read column 0 and never
+        // use it): a select after each 16-bit load made the compiler branch
+        // around it and wait for it, one round trip per value
         const int64_t base = e * NP + (gll ? L : 0);
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) uc[k] = gll ? ld<TC>(u, base + k * NC) : TC(0);
+        for (int k = 0; k < NQ; ++k) uc[k] = ld<TC>(u, base + k * NC);
     }
     // wJ pieces: 8-byte pieces for FP64 data, dwords otherwise (16-bit values:
     // the dwords wholly inside the element plus a half-filled first one; a

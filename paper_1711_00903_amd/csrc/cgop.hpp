@@ -117,15 +117,19 @@ __global__ __launch_bounds__(threads_for(0, NQ, EPB)) void cgop_kernel(
         // p (with the direction update) for this GLL column
         TC uc[NQ];
         if (okc) {
+            // p and r requested together before the update (with the update
+            // inside the same loop, each r load was waited for right away)
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-                TC v = p[base + k * NC];
-                if (do_xpay) v = r[base + k * NC] + beta * v;
-                uc[k] = v;
-            }
+            for (int k = 0; k < NQ; ++k) uc[k] = p[base + k * NC];
             if (do_xpay) {
+                TC rv[NQ];
 #pragma unroll
-                for (int k = 0; k < NQ; ++k) p[base + k * NC] = uc[k];
+                for (int k = 0; k < NQ; ++k) rv[k] = r[base + k * NC];
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    uc[k] = rv[k] + beta * uc[k];
+                    p[base + k * NC] = uc[k];
+                }
             }
         } else {
 #pragma unroll
