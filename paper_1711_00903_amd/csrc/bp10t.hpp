@@ -81,13 +81,19 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
     constexpr bool TLDS = NQ >= 12;
     // FP64 from Nq = 11: an empty asm with a memory clobber between line
     // products that share a table (the r-direction's interpolation and
-    // projection; from Nq = 13 also the lines of consecutive passes) makes each
+    // projection; from Nq = 12 also the lines of the s-direction) makes each
     // read the table again instead of the compiler holding the first one's
     // values in registers for the next (measured at E = 65536: Nq = 11 3.3 ->
     // 3.9, Nq = 12 3.2 -> 3.7 (with the tables in LDS), Nq = 13 2.8 -> 3.1,
-    // Nq = 14 2.5 -> 3.0, Nq = 15 2.4 -> 3.0 TB/s).
+    // Nq = 14 2.5 -> 3.0, Nq = 15 2.4 -> 3.0 TB/s).  In FP32 arithmetic the
+    // same fences cut the registers (Nq = 13: 135 -> 84 VGPRs) but measured
+    // no faster at Nq = 12..15 and 10% slower at Nq = 16 (E = 262144).
     constexpr bool FENCE_R = sizeof(TC) == 8 && NQ >= 11;
     constexpr bool FENCE_S = sizeof(TC) == 8 && NQ >= 12;
+    // FP64 at Nq = 13: the u column is kept live to the end of the element, as
+    // the CG form (DOT) keeps it; the register allocator then fits the kernel
+    // in 154 VGPRs (three waves per SIMD) instead of 182 (two)
+    constexpr bool PIN_U = !DOT && sizeof(TC) == 8 && NQ == 13;
     constexpr int IOR = GE > 0 ? GE : 1, IOC = QE > 0 ? QE : 1;
     __shared__ TC sIe[TLDS ? HG : 1][HQ];
     __shared__ TC sIo[TLDS ? IOR : 1][IOC];
@@ -284,6 +290,10 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
             if (beta != TC(0)) r += beta * yold[k];
             y[idx] = static_cast<TY>(r);
             if constexpr (DOT) dp += uc[k] * r;
+        }
+        if constexpr (PIN_U) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) asm volatile("" ::"v"(uc[k]));
         }
     }
     if constexpr (DOT) {

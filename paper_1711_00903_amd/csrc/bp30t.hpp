@@ -78,6 +78,11 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
     // kept apart (FENCE, below), which fit the kernel in two waves per SIMD
     // (Nq = 10: 3.9 -> 4.5 TB/s, Nq = 12: 3.0 -> 4.1 TB/s at E = 65536).
     constexpr bool FENCE = sizeof(TC) == 8 && NQ >= 10;
+    // FP32 arithmetic at Nq = 14: the same fences without the FP64 prefetch and
+    // table choices (230 -> 150 VGPRs, two -> three waves per SIMD; 12% faster
+    // at E = 262144 with FP32, BF16 and FP16 storage; at Nq = 12, 13, 15 and 16
+    // they cut registers too but measured 4-10% slower)
+    constexpr bool FENCE32 = sizeof(TC) == 4 && NQ == 14;
     constexpr bool TLDS = FENCE || NQ > 12 || NQ == 11 || (NQ == 12 && sizeof(TC) == 4);
     constexpr int QEC = QE > 0 ? QE : 1;
     __shared__ TC sIe[TLDS ? HG : 1][HQ];
@@ -183,7 +188,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
         // the second read its LDS half tables again: otherwise the compiler
         // keeps the first product's table values live in registers for the
         // second (at Ng = 16 that alone pushed the kernel to one wave per SIMD).
-        if constexpr (FENCE) asm volatile("" ::: "memory");
+        if constexpr (FENCE || FENCE32) asm volatile("" ::: "memory");
 #pragma unroll
         for (int m = 0; m < NG; ++m) x[m] = V2[c * S + m * P + p];   // column (a = p)
         line_deriv<NG>(x, z, Dp, Dm);
@@ -199,12 +204,12 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
 #pragma unroll
         for (int c = 0; c < NG; ++c) ut[c] = V2[c * S + o];
         line_deriv<NG>(ut, qt, Dp, Dm);
-        if constexpr (FENCE) asm volatile("" ::: "memory");
+        if constexpr (FENCE || FENCE32) asm volatile("" ::: "memory");
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             // one slab at a time: without the barrier the scheduler hoists the
             // later slabs' loads and LDS reads and holds them all in registers
-            if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (FENCE || FENCE32) __builtin_amdgcn_sched_barrier(0);
             if (c + GPRE < NG) gload(c + GPRE);
             const TC qr = V0[c * S + o], qs = V1[c * S + o];
             const TC grr = to_compute(g[0][c], TC{}), grs = to_compute(g[1][c], TC{}),
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(bp30t_threads(NQ)) void bp30t_kernel(
             V1[c * S + o] = grs * qr + gss * qs + gst * qt[c];
             wt[c] = grt * qr + gst * qs + gtt * qt[c];
         }
-        if constexpr (FENCE) asm volatile("" ::: "memory");
+        if constexpr (FENCE || FENCE32) asm volatile("" ::: "memory");
         line_deriv_t<NG>(wt, vt, Dp, Dm);
         if (lambda != TC(0)) {
             // u~ is read again from this lane's own column of V2 instead of

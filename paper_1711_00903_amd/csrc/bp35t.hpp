@@ -56,12 +56,14 @@ __attribute__((amdgpu_waves_per_eu(bp35t_min_waves(NQ)))) void bp35t_kernel(
     // beyond Nq = 11, where three no longer fit in registers)
     constexpr int GPRE = NV < 3 ? NV : (sizeof(TC) == 8 && NQ >= 12 ? 2 : 3);
     static_assert(NQ >= 2 && NC <= bp35t_threads(NQ), "one lane per GLL column");
-    // FP64 from Nq = 12: an empty asm with a memory clobber between two line
+    // From Nq = 12: an empty asm with a memory clobber between two line
     // products makes the second read its LDS half tables again; otherwise the
     // compiler holds the first product's table values in registers for the
-    // second, which cost a wave per SIMD (measured at E = 65536: Nq = 12 4.0 ->
-    // 5.1, Nq = 14 2.6 -> 5.1, Nq = 16 3.3 -> 5.7 TB/s).
-    constexpr bool FENCE = sizeof(TC) == 8 && NQ >= 12;
+    // second, which cost a wave per SIMD (FP64, measured at E = 65536: Nq = 12
+    // 4.0 -> 5.1, Nq = 14 2.6 -> 5.1, Nq = 16 3.3 -> 5.7 TB/s; FP32 arithmetic
+    // with 16-bit storage at E = 262144: Nq = 13 3.3 -> 2.4 ms, Nq = 14 3.8 ->
+    // 3.0, Nq = 15 4.5 -> 3.7, with FP32 storage unchanged).
+    constexpr bool FENCE = NQ >= 12;
 
     __shared__ __align__(16) TC V0[VOL];
     __shared__ __align__(16) TC V1[VOL];
