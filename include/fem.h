@@ -238,8 +238,8 @@ typedef struct {
 } fem_cg_operator;
 
 /* How one Krylov iteration's p <- r + beta p, Ap = (S + lambda M) p and p . Ap
- * are split into kernels.  AUTO: two kernels where available (FP64 vectors,
- * N <= 7, lambda != 0) -- the stiffness kernel forms p as it loads it and
+ * are split into kernels.  AUTO: two kernels where available (FP64 or FP32
+ * vectors, N <= 7, lambda != 0) -- the stiffness kernel forms p as it loads it and
  * writes it back, the mass kernel adds lambda M p and emits per-element
  * partials of p . Ap -- else as NONE.  NONE: one kernel per step.  ONEPASS: a
  * single kernel for the three steps (FP64 vectors, lambda != 0, N <= 14),

@@ -64,8 +64,17 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
 
     // A: t-interpolated field [c][j][i], then the staged wJ, then the
     // s-projected field [c][j][i].  B: s-interpolated field [c][b][i], turned
-    // in place into the r-direction result [c][b][i].
-    constexpr int WBYTES = NPG * static_cast<int>(sizeof(TG)) + 8;   // staged wJ (+ misalignment slack)
+    // in place into the r-direction result [c][b][i].  The staged wJ keeps its
+    // stored type.  Where Ng W (the interleave) times the value size is a
+    // multiple of 256 bytes (Ng = 16), the lanes of an r-direction pass,
+    // reading it in its global layout, all fall on one bank (an LDS conflict
+    // ratio of 0.72 for BF16 at N = 14): there it is staged in rows [c][b][a]
+    // of odd length PW (6-8% faster).  Elsewhere the remap costs more than the
+    // conflicts (5-20% slower) and the pieces are copied as they are.
+    constexpr bool REMAP = bp10t_remap_w(NG, static_cast<int>(sizeof(TG)));
+    constexpr int PW = bp10t_wrow(NG);
+    constexpr int WBYTES = REMAP ? NG * NG * PW * static_cast<int>(sizeof(TG))
+                                 : NPG * static_cast<int>(sizeof(TG)) + 8;   // (+ misalignment slack)
     constexpr int AV = NG * SA;
     constexpr int A_VALUES = AV * static_cast<int>(sizeof(TC)) > WBYTES ? AV
                                                                         : (WBYTES + sizeof(TC) - 1) / sizeof(TC);
@@ -213,7 +222,7 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
         }
     }
     __syncthreads();   // A is free: stage wJ there
-    {
+    if constexpr (!REMAP) {
         Piece *sw = reinterpret_cast<Piece *>(sA);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
@@ -221,12 +230,39 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
             if (t < np) sw[t] = wst[q];
         }
         if (tail && L == 0) reinterpret_cast<uint16_t *>(sA)[off + NPG - 1] = wlast;
+    } else {
+        TG *sw = reinterpret_cast<TG *>(sA);
+        // value v of the element (its stored layout) -> row (c, b), entry a
+        auto put = [&](int v, TG val) {
+            const int q = v / W, c = (q / (NG * NG)) * W + v % W, col = q % (NG * NG);
+            sw[(c * NG + col / NG) * PW + col % NG] = val;
+        };
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const int t = L + q * NT;
+            if (t < np) {
+                TG vals[VPP];
+                __builtin_memcpy(vals, &wst[q], sizeof(Piece));
+#pragma unroll
+                for (int r = 0; r < VPP; ++r) {
+                    const int v = t * VPP + r - off;
+                    if (v >= 0 && v < NPG) put(v, vals[r]);
+                }
+            }
+        }
+        if constexpr (VPP == 2) {
+            if (tail && L == 0) {
+                TG last;
+                __builtin_memcpy(&last, &wlast, sizeof(TG));
+                put(NPG - 1, last);
+            }
+        }
     }
     __syncthreads();
 
     // r-direction: lines (b,c): interpolate, scale by wJ, project, in place
     {
-        const TG *sw = reinterpret_cast<const TG *>(sA) + off;
+        const TG *sw = reinterpret_cast<const TG *>(sA) + (REMAP ? 0 : off);
 #pragma unroll
         for (int pass = 0; pass < (NG * NG + NT - 1) / NT; ++pass) {
             const int line = L + pass * NT;
@@ -239,7 +275,8 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
                 if constexpr (FENCE_R) asm volatile("" ::: "memory");
                 line_interp<NQ>(x, z, Ie, Io);
 #pragma unroll
-                for (int a = 0; a < NG; ++a) z[a] *= to_compute(sw[geo_offset(a + NG * b, c, NG, W)], TC{});
+                for (int a = 0; a < NG; ++a)
+                    z[a] *= to_compute(sw[REMAP ? (c * NG + b) * PW + a : geo_offset(a + NG * b, c, NG, W)], TC{});
                 if constexpr (FENCE_R) asm volatile("" ::: "memory");
                 line_project<NQ>(z, w, Ie, Io);
 #pragma unroll
@@ -289,7 +326,7 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
             const int64_t idx = base + k * NC;
             if (beta != TC(0)) r += beta * yold[k];
             y[idx] = static_cast<TY>(r);
-            if constexpr (DOT) dp += uc[k] * r;
+            if constexpr (DOT) dp += static_cast<double>(uc[k]) * static_cast<double>(r);
         }
         if constexpr (PIN_U) {
 #pragma unroll
@@ -297,7 +334,8 @@ __global__ __launch_bounds__(bp10t_threads(NQ)) void bp10t_kernel(
         }
     }
     if constexpr (DOT) {
-        static_assert(std::is_same<TV, double>::value, "element partials of FP64 fields");
+        static_assert(std::is_same<TV, double>::value || std::is_same<TV, float>::value,
+                      "element partials of FP64 or FP32 fields");
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
         if constexpr (NT == kWave) {
@@ -323,7 +361,8 @@ hipError_t bp10t_launch_t(const ApplyArgs &a, hipStream_t s)
     using TC = typename compute_pair<TG, TV>::type;
     using TY = typename output_of<TV>::type;
     if (a.E < 1) return hipSuccess;
-    if (a.part && !std::is_same<TV, double>::value) return hipErrorInvalidValue;
+    if (a.part && !(std::is_same<TV, double>::value || (std::is_same<TV, float>::value && NQ <= 8)))
+        return hipErrorInvalidValue;
     const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
                                                                          : a.out_scale);
     // one workgroup per element; a grid cap splits the elements over launches
@@ -331,7 +370,7 @@ hipError_t bp10t_launch_t(const ApplyArgs &a, hipStream_t s)
     if (chunk > max_grid(bp10t_threads(NQ))) chunk = max_grid(bp10t_threads(NQ));
     for (int64_t e0 = 0; e0 < a.E; e0 += chunk) {
         const unsigned grid = static_cast<unsigned>(a.E - e0 < chunk ? a.E - e0 : chunk);
-        if constexpr (std::is_same<TV, double>::value) {
+        if constexpr (std::is_same<TV, double>::value || (std::is_same<TV, float>::value && NQ <= 8)) {
             if (a.part) {
                 hipLaunchKernelGGL((bp10t_kernel<NQ, TG, TV, true>), dim3(grid), dim3(bp10t_threads(NQ)), 0, s, a.E, a.I1d,
                                    static_cast<const TG *>(a.wJ), static_cast<const TV *>(a.u),

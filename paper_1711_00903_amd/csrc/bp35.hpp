@@ -168,9 +168,10 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         // before the field reaches LDS.
         TC uc[NQ];
         if constexpr (XP) {
-            static_assert(std::is_same<TV, double>::value, "direction update on FP64 fields");
-            const double bp = *xbeta;
-            double rv[NQ];
+            static_assert(std::is_same<TV, double>::value || std::is_same<TV, float>::value,
+                          "direction update on FP64 or FP32 fields");
+            const TC bp = static_cast<TC>(*xbeta);   // in the vectors' precision, as xpay_kernel
+            TV rv[NQ];
 #pragma unroll
             for (int k = 0; k < NQ; ++k) {
                 uc[k] = pw[base + k * NC];
@@ -331,14 +332,17 @@ hipError_t bp35_launch_t(const ApplyArgs &a, hipStream_t s)
     if (grid < 1) return hipSuccess;
     const TC oscale = static_cast<TC>(is_f16_prec(a.prec) ? a.out_scale / a.geo_scale
                                                                          : a.out_scale);
-    if constexpr (std::is_same<TV, double>::value) {
+    // the direction update: FP64 fields at every degree the CG split serves,
+    // FP32 fields (the iterative-refinement inner CG) likewise
+    if constexpr (std::is_same<TV, double>::value || (std::is_same<TV, float>::value && NQ <= 8)) {
         if (a.xr) {
             hipLaunchKernelGGL((bp35_kernel<NQ, EPB, TG, TV, true>), dim3(static_cast<unsigned>(grid)),
                                dim3(threads_for(1, NQ, EPB)), 0, s, a.E, ngroups, a.D1d,
                                static_cast<const TG *>(a.G), static_cast<const TG *>(a.wJ),
                                static_cast<TC>(a.lambda), static_cast<const TV *>(a.u),
                                static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale,
-                               static_cast<TV *>(const_cast<void *>(a.u)), a.xr, a.xbeta);
+                               static_cast<TV *>(const_cast<void *>(a.u)), static_cast<const TV *>(a.xr),
+                               a.xbeta);
             return hipGetLastError();
         }
     }

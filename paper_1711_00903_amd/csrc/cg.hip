@@ -316,11 +316,11 @@ hipError_t apply_A(const Ctx &c, int prec, const void *u, void *y)
     return launch_bp10(a, c.s);
 }
 
-// Two-kernel Krylov operator on FP64 vectors: the stiffness kernel applies the
-// direction update u <- r + (*beta) u as it loads u (when r is set), the mass
-// kernel (one-wave BP1.0) adds lambda M u and writes per-element partials of
-// u . y into epart.  Requires N <= 7 and lambda != 0.
-hipError_t apply_A_split(const Ctx &c, int prec, const double *r, const double *beta, double *u, double *y,
+// Two-kernel Krylov operator on FP64 or FP32 vectors: the stiffness kernel
+// applies the direction update u <- r + (*beta) u as it loads u (when r is
+// set), the mass kernel (one-wave BP1.0) adds lambda M u and writes
+// per-element partials of u . y into epart.  Requires N <= 7 and lambda != 0.
+hipError_t apply_A_split(const Ctx &c, int prec, const void *r, const double *beta, void *u, void *y,
                          double *epart)
 {
     const fem_cg_operator *op = c.op;
@@ -397,10 +397,11 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     const int64_t n = op->E * np;
     const int64_t groups = cg_groups(op->N, op->E);
     const Layout L = layout(n, sizeof(TV), groups);
-    // the fused forms need FP64 vectors and a mass term
+    // the one-pass form needs FP64 vectors and a mass term, the two-kernel
+    // form a mass term
     const bool f64v = std::is_same<TV, double>::value && op->lambda != 0.0;
     const bool fused = f64v && opt->fusion == FEM_CG_FUSE_ONEPASS && cgop_supported(op->N);
-    const bool split = f64v && opt->fusion == FEM_CG_FUSE_AUTO && split_supported(op->N);
+    const bool split = op->lambda != 0.0 && opt->fusion == FEM_CG_FUSE_AUTO && split_supported(op->N);
     char *w = static_cast<char *>(ws);
     double *r = reinterpret_cast<double *>(w + L.r);
     double *tmp = reinterpret_cast<double *>(w + L.tmp);
@@ -489,8 +490,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                 return FEM_ERR_HIP;
             fin(partg, cgop_groups(op->N, op->E), &sc->pAp, FIN_ALPHA);
         } else if (split) {
-            if (apply_A_split(c, prec_lo, xpay ? reinterpret_cast<const double *>(rl) : nullptr, &sc->beta,
-                              reinterpret_cast<double *>(p), reinterpret_cast<double *>(Ap), partg) != hipSuccess)
+            if (apply_A_split(c, prec_lo, xpay ? rl : nullptr, &sc->beta, p, Ap, partg) != hipSuccess)
                 return FEM_ERR_HIP;
             hipLaunchKernelGGL(sum_kernel, G, B, 0, s, partg, op->E, part);
             fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);

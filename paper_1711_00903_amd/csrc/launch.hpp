@@ -48,12 +48,12 @@ struct ApplyArgs {
     int prec;
     int epb;             // elements per workgroup, 0 = default
     int grid_cap;        // max workgroups, 0 = uncapped
-    // Conjugate-gradient extensions (FP64 fields only).  BP3.5 with xr set
-    // first replaces u in place by xr + (*xbeta) u (the direction update) and
-    // applies the operator to the result.  BP1.0 (one-wave kernel) with part
-    // set writes part[e] = sum over element e's nodes of u * y, y the final
-    // output.
-    const double *xr = nullptr;
+    // Conjugate-gradient extensions (FP64 or FP32 fields; xr has the fields'
+    // type).  BP3.5 with xr set first replaces u in place by xr + (*xbeta) u
+    // (the direction update) and applies the operator to the result.  BP1.0
+    // (one-wave kernel) with part set writes part[e] = sum over element e's
+    // nodes of u * y (products and sum in FP64), y the final output.
+    const void *xr = nullptr;
     const double *xbeta = nullptr;
     double *part = nullptr;
 };

@@ -48,12 +48,20 @@ constexpr int interp_half_values(int nq)
 // 80 KB of LDS (two workgroups per CU).
 constexpr int bp10t_row(int nq, int bytes) { return bytes == 8 && nq == 16 ? 17 : lds_row(nq, bytes); }
 
+// The BP1.0 line kernel stages the scaled Jacobians in rows of odd length
+// (so the lanes of an r-direction pass, one row apart, fall on distinct
+// banks) where their stored layout puts those lanes 256 bytes apart: Ng W
+// bytes a multiple of 256 (Ng = 16 for every value size).
+constexpr bool bp10t_remap_w(int ng, int gbytes) { return (ng * geo_vec(ng, gbytes) * gbytes) % 256 == 0; }
+constexpr int bp10t_wrow(int ng) { return ng | 1; }
+
 constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 {
     const int ng = nq + 1;
     const int p = bp10t_row(nq, bytes);
-    const int av = ng * nq * p;                                       // [c][j][i] volume
-    const int wv = (ng * ng * ng * gbytes + 8 + bytes - 1) / bytes;   // staged scaled Jacobians
+    const int av = ng * nq * p;                                                // [c][j][i] volume
+    const int wv = bp10t_remap_w(ng, gbytes) ? (ng * ng * bp10t_wrow(ng) * gbytes + bytes - 1) / bytes
+                                             : (ng * ng * ng * gbytes + 8 + bytes - 1) / bytes;   // staged wJ
     const int tab = nq >= 12 ? interp_half_values(nq) : 0;   // LDS tables
     return ((av > wv ? av : wv) + ng * ng * p + tab) * bytes;
 }

@@ -148,8 +148,9 @@ def test_iterative_refinement_converges(setup, inner):
     assert true_relative_residual(A, bo, x.cpu().numpy()) <= 1.1 * rtol
 
 
+@pytest.mark.parametrize("fusion", [0, 1])   # two kernels with FP32 vectors, one kernel per step
 @pytest.mark.parametrize("inner", [1, 4, 5])
-def test_iterative_refinement_fp32_inner(setup, inner):
+def test_iterative_refinement_fp32_inner(setup, inner, fusion):
     """FP32 vectors and arithmetic in the inner CG (u, G stored FP32, BF16 or
     FP16) with lambda = 4096 (condition number ~1e3, so kappa * eps32 << 1):
     the refinement reaches 1e-8; the oracle confirms the residual, and the
@@ -160,9 +161,10 @@ def test_iterative_refinement_fp32_inner(setup, inner):
     pb = oracle.Problem(N, X)
     A4 = lambda v: pb.cg_operator(v, lam)
     x = torch.zeros_like(bt)
-    rep = dev.cg_solve(bt, x, lam=lam, mode=2, inner_prec=inner, rtol=rtol, delta=0.1, max_iters=5000)
+    rep = dev.cg_solve(bt, x, lam=lam, mode=2, inner_prec=inner, rtol=rtol, delta=0.1, max_iters=5000,
+                       fusion=fusion)
     torch.cuda.synchronize()
-    print(f"IR FP32 inner={inner}: {rep}")
+    print(f"IR FP32 inner={inner} fusion={fusion}: {rep}")
     res = true_relative_residual(A4, bo, x.cpu().numpy())
     assert abs(rep["rel_res"] - res) <= 1e-3 * res + 1e-14
     assert rep["status"] == fem.FEM_OK and res <= 1.1 * rtol, (rep, res)
