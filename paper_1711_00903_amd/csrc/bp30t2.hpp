@@ -36,8 +36,11 @@ namespace fem {
 // at Ng = 17.  There, asking the register allocator for three waves per SIMD
 // (two five-wave workgroups per CU) measured 2% faster but spilled 120 bytes
 // per lane, which went to HBM as scratch traffic; the kernel runs without.
+// At Nq = 12 the request (172 -> 168 VGPRs, 28 bytes of spill) lets four
+// workgroups share a CU instead of two: 4.05 -> 3.87 ms at E = 131072, against
+// 4.15 ms for the three-volume kernel, with the same bits.
 constexpr int bp30t2_gpre(int nq) { return nq >= 16 ? 1 : 2; }
-constexpr int bp30t2_min_waves(int nq) { return 1; }
+constexpr int bp30t2_min_waves(int nq) { return nq == 12 ? 3 : 1; }
 
 template <int NQ, class TG, class TV>
 __global__ __launch_bounds__(bp30t_threads(NQ))

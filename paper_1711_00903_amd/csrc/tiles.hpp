@@ -68,12 +68,12 @@ constexpr int bp10t_lds_bytes(int nq, int bytes, int gbytes)
 
 // BP3.0 with one element per workgroup runs the line-per-lane kernel
 // (bp30t.hpp): one lane per Gauss column, three Ng^3 LDS volumes -- or two
-// (bp30t2.hpp) in FP64 arithmetic at Nq = 11 and from Nq = 13, where the third
-// volume kept a second workgroup off the CU (measured at E = 65536: Nq = 11
-// 2.6 -> 4.1, Nq = 13 2.7 -> 4.2, Nq = 14 2.8 -> 4.1, Nq = 15 3.4 -> 4.4,
-// Nq = 16 1.5 -> 3.0 TB/s).
+// (bp30t2.hpp) in FP64 arithmetic from Nq = 11, where the third volume kept a
+// second workgroup off the CU (measured at E = 65536: Nq = 11 2.6 -> 4.1,
+// Nq = 13 2.7 -> 4.2, Nq = 14 2.8 -> 4.1, Nq = 15 3.4 -> 4.4, Nq = 16 1.5 ->
+// 3.0 TB/s; Nq = 12 at E = 131072: 4.15 -> 3.87 ms with three waves per SIMD).
 constexpr bool bp30_line(int nq, int epb) { return epb == 1; }
-constexpr bool bp30t_two_volumes(int nq, int bytes) { return bytes == 8 && (nq == 11 || nq >= 13); }
+constexpr bool bp30t_two_volumes(int nq, int bytes) { return bytes == 8 && nq >= 11; }
 
 constexpr int bp30t_lds_bytes(int nq, int bytes)
 {

@@ -59,7 +59,7 @@ def kernel_family(op: str, N: int, epb: int, prec: int = fem.FEM_F64) -> str:
         return "bp35t" if epb == 1 and N + 1 >= 11 else "bp35"
     if epb != 1:
         return "bp30"
-    return "bp30t2" if prec in _F64_FIELDS and (N + 1 == 11 or N + 1 >= 13) else "bp30t"
+    return "bp30t2" if prec in _F64_FIELDS and N + 1 >= 11 else "bp30t"
 
 
 def lds_values(family: str, N: int) -> tuple[int, int]:
