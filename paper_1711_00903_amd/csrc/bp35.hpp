@@ -100,7 +100,8 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
     const TG *__restrict__ wJ, typename compute_pair<TG, TV>::type lambda, const TV *__restrict__ u,
     typename output_of<TV>::type *__restrict__ y, typename compute_pair<TG, TV>::type beta,
     typename compute_pair<TG, TV>::type oscale, TV *pw = nullptr, const TV *__restrict__ xr = nullptr,
-    const double *__restrict__ xbeta = nullptr)
+    const double *__restrict__ xbeta = nullptr, TV *__restrict__ xlo = nullptr,
+    const double *__restrict__ xalpha = nullptr)
 {
     using TC = typename compute_pair<TG, TV>::type;
     using TY = typename output_of<TV>::type;
@@ -171,14 +172,26 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
             static_assert(std::is_same<TV, double>::value || std::is_same<TV, float>::value,
                           "direction update on FP64 or FP32 fields");
             const TC bp = static_cast<TC>(*xbeta);   // in the vectors' precision, as xpay_kernel
-            TV rv[NQ];
+            // with xlo set, the previous step's iterate update x_lo += alpha p
+            // is folded in here, on the p it read before replacing it
+            const bool fold = xlo != nullptr;
+            TV rv[NQ], xv[NQ];
 #pragma unroll
             for (int k = 0; k < NQ; ++k) {
                 uc[k] = pw[base + k * NC];
                 rv[k] = xr[base + k * NC];
             }
+            if (fold) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) xv[k] = xlo[base + k * NC];
+            }
+            const TC al = fold ? static_cast<TC>(*xalpha) : TC(0);
 #pragma unroll
             for (int k = 0; k < NQ; ++k) {
+                if (fold) {
+                    xv[k] += al * uc[k];
+                    if (ok) xlo[base + k * NC] = xv[k];
+                }
                 uc[k] = rv[k] + bp * uc[k];
                 if (ok) pw[base + k * NC] = uc[k];
             }
@@ -342,7 +355,7 @@ hipError_t bp35_launch_t(const ApplyArgs &a, hipStream_t s)
                                static_cast<TC>(a.lambda), static_cast<const TV *>(a.u),
                                static_cast<TY *>(a.y), static_cast<TC>(a.beta), oscale,
                                static_cast<TV *>(const_cast<void *>(a.u)), static_cast<const TV *>(a.xr),
-                               a.xbeta);
+                               a.xbeta, static_cast<TV *>(a.xl), a.xalpha);
             return hipGetLastError();
         }
     }

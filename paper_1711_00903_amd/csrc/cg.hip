@@ -103,7 +103,9 @@ __global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double *__r
     }
 }
 
-// x_lo += alpha p; r_lo -= alpha Ap; per-block partial sums of r_lo . r_lo.
+// x_lo += alpha p (unless UPD_X is false: the two-kernel step folds it into
+// the next direction update); r_lo -= alpha Ap; per-block partial sums of
+// r_lo . r_lo.
 // Non-persistent: block b owns kUpdPairs * kRedThreads consecutive pairs of
 // entries (16-byte vectors for FP64), every thread issues all its loads before
 // its first store (the streaming-copy pattern; a grid-stride loop over the
@@ -118,7 +120,7 @@ inline int64_t update_blocks(int64_t n)
     return b > 0 ? b : 1;
 }
 
-template <class TV>
+template <class TV, bool UPD_X = true>
 __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl, TV *__restrict__ rl,
                                                              const TV *__restrict__ p,
                                                              const TV *__restrict__ Ap, int64_t n,
@@ -139,9 +141,11 @@ __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl
     for (int q = 0; q < kUpdPairs; ++q) {
         const int64_t i = i0 + q * kRedThreads;
         if (i < n2) {
-            pv[q] = p2[i];
+            if constexpr (UPD_X) {
+                pv[q] = p2[i];
+                xv[q] = x2[i];
+            }
             av[q] = a2[i];
-            xv[q] = x2[i];
             rv[q] = r2[i];
         }
     }
@@ -150,9 +154,11 @@ __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl
     for (int q = 0; q < kUpdPairs; ++q) {
         const int64_t i = i0 + q * kRedThreads;
         if (i < n2) {
-            xv[q] += alpha * pv[q];
             rv[q] -= alpha * av[q];
-            x2[i] = xv[q];
+            if constexpr (UPD_X) {
+                xv[q] += alpha * pv[q];
+                x2[i] = xv[q];
+            }
             r2[i] = rv[q];
             s += static_cast<double>(rv[q].x) * static_cast<double>(rv[q].x);
             s += static_cast<double>(rv[q].y) * static_cast<double>(rv[q].y);
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(kRedThreads) void update_kernel(TV *__restrict__ xl
     }
     if ((n & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         const int64_t i = n - 1;
-        xl[i] += alpha * p[i];
+        if constexpr (UPD_X) xl[i] += alpha * p[i];
         const TV r = rl[i] - alpha * Ap[i];
         rl[i] = r;
         s += static_cast<double>(r) * static_cast<double>(r);
@@ -178,6 +184,17 @@ __global__ __launch_bounds__(kRedThreads) void xpay_kernel(TV *__restrict__ p, c
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kRedThreads)
         p[i] = rl[i] + beta * p[i];
+}
+
+// x_lo += alpha p: the iterate update still pending from a two-kernel step
+template <class TV>
+__global__ __launch_bounds__(kRedThreads) void axpy_kernel(TV *__restrict__ xl, const TV *__restrict__ p,
+                                                           int64_t n, const CgScalars *__restrict__ sc)
+{
+    const TV alpha = static_cast<TV>(sc->alpha);
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads)
+        xl[i] += alpha * p[i];
 }
 
 // x += x_lo; x_lo = 0
@@ -321,7 +338,7 @@ hipError_t apply_A(const Ctx &c, int prec, const void *u, void *y)
 // set), the mass kernel (one-wave BP1.0) adds lambda M u and writes
 // per-element partials of u . y into epart.  Requires N <= 7 and lambda != 0.
 hipError_t apply_A_split(const Ctx &c, int prec, const void *r, const double *beta, void *u, void *y,
-                         double *epart)
+                         double *epart, void *xl, const double *alpha)
 {
     const fem_cg_operator *op = c.op;
     const bool hi = prec == FEM_F64;
@@ -338,6 +355,8 @@ hipError_t apply_A_split(const Ctx &c, int prec, const void *r, const double *be
     a.geo_scale = op->geo_scale_G;
     a.xr = r;
     a.xbeta = beta;
+    a.xl = r ? xl : nullptr;
+    a.xalpha = alpha;
     fem_tune_get(OP_BP35, a.N, prec, &a.epb, &a.grid_cap);
     hipError_t e = launch_bp35(a, c.s);
     if (e != hipSuccess) return e;
@@ -349,6 +368,8 @@ hipError_t apply_A_split(const Ctx &c, int prec, const void *r, const double *be
     a.geo_scale = op->geo_scale_wJ;
     a.xr = nullptr;
     a.xbeta = nullptr;
+    a.xl = nullptr;
+    a.xalpha = nullptr;
     a.part = epart;
     a.epb = 1;          // the one-wave kernel
     a.grid_cap = 0;
@@ -478,6 +499,14 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     // in the low precision, stopped when it has reduced the residual by delta
     const bool restart_ir = opt->mode == 2;
     bool fresh = true;   // p = r_lo already: no direction update in the next step
+    // two-kernel step: the update kernel leaves x_lo alone and the next
+    // direction update adds alpha p into it; `pending` marks a step whose
+    // alpha p is still to be added (flushed before x_lo is used or p replaced)
+    bool pending = false;
+    auto flush = [&]() {
+        if (pending) hipLaunchKernelGGL(axpy_kernel<TV>, G, B, 0, s, xl, p, n, sc);
+        pending = false;
+    };
     int it = 0;
     while (!converged && it < opt->max_iters) {
         ++it;
@@ -490,8 +519,11 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                 return FEM_ERR_HIP;
             fin(partg, cgop_groups(op->N, op->E), &sc->pAp, FIN_ALPHA);
         } else if (split) {
-            if (apply_A_split(c, prec_lo, xpay ? rl : nullptr, &sc->beta, p, Ap, partg) != hipSuccess)
+            if (!xpay) flush();
+            if (apply_A_split(c, prec_lo, xpay ? rl : nullptr, &sc->beta, p, Ap, partg, pending ? xl : nullptr,
+                              &sc->alpha) != hipSuccess)
                 return FEM_ERR_HIP;
+            pending = false;
             hipLaunchKernelGGL(sum_kernel, G, B, 0, s, partg, op->E, part);
             fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
         } else {
@@ -500,8 +532,14 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
             hipLaunchKernelGGL((dot_kernel<TV, TV>), G, B, 0, s, p, Ap, n, part);
             fin(part, kRedBlocks, &sc->pAp, FIN_ALPHA);
         }
-        hipLaunchKernelGGL(update_kernel<TV>, dim3(static_cast<unsigned>(update_blocks(n))), B, 0, s, xl, rl, p,
-                           Ap, n, sc, partg);
+        if (split) {
+            hipLaunchKernelGGL((update_kernel<TV, false>), dim3(static_cast<unsigned>(update_blocks(n))), B, 0, s,
+                               xl, rl, p, Ap, n, sc, partg);
+            pending = true;
+        } else {
+            hipLaunchKernelGGL((update_kernel<TV, true>), dim3(static_cast<unsigned>(update_blocks(n))), B, 0, s,
+                               xl, rl, p, Ap, n, sc, partg);
+        }
         hipLaunchKernelGGL(sum_kernel, G, B, 0, s, partg, update_blocks(n), part2);
         fin(part2, kRedBlocks, &sc->rr_new, FIN_PLAIN);
         if (it % every == 0 || it == opt->max_iters) {
@@ -515,6 +553,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
                 const bool by_target = !(rn < delta * rmax);
                 // reliable update: fold the low-precision iterate into x and
                 // replace the recursive residual by the true one
+                flush();
                 hipLaunchKernelGGL(merge_kernel<TV>, G, B, 0, s, x, xl, n);
                 if (true_residual(restart_ir) != hipSuccess) return FEM_ERR_HIP;
                 fresh = restart_ir;
@@ -539,6 +578,7 @@ int solve_t(const fem_cg_operator *op, const fem_cg_options *opt, int prec_lo, c
     }
     if (!converged) {
         // fold in the last low-precision iterate and report the true residual
+        flush();
         hipLaunchKernelGGL(merge_kernel<TV>, G, B, 0, s, x, xl, n);
         if (true_residual(false) != hipSuccess) return FEM_ERR_HIP;
         rep->hi_matvecs += 1;

@@ -55,6 +55,10 @@ struct ApplyArgs {
     // nodes of u * y (products and sum in FP64), y the final output.
     const void *xr = nullptr;
     const double *xbeta = nullptr;
+    // With xr and xl set, BP3.5 also adds (*xalpha) u (u before the direction
+    // update) into xl: the iterate update of the previous Krylov step.
+    void *xl = nullptr;
+    const double *xalpha = nullptr;
     double *part = nullptr;
 };
 
