@@ -93,6 +93,24 @@ __attribute__((amdgpu_waves_per_eu(bp30_min_waves(NQ, EPB)))) void bp30_kernel(
         }
         const int64_t e = e0 + slot;
         const bool ok = lane && e < E;
+        const TG *Ge = G + (ok ? e : 0) * (6 * NPG) + col * W;
+        // Ng <= 5: all of the column's factors are requested here, together
+        // with u, and kept in their stored type until the metric step; loaded
+        // there, slab by slab, each request was waited for in turn after the
+        // interpolations (one exposed round trip per W slabs at low degree).
+        // Plain loads: a slab of Ng^2 W values is a fraction of a 128-byte
+        // line, and non-temporal requests for the slabs sharing a line fetched
+        // it from HBM once each (1.95x the algorithmic bytes at N = 1).  FP64
+        // factors at Ng = 4 stay on the slab path (8% slower prefetched).
+        constexpr bool GPREF = NG <= 3 || (NG <= 5 && sizeof(TG) < 8);
+        constexpr int NVG = NG / W;
+        packed_vec<W, TG> gpv[GPREF ? 6 * NVG : 1];
+        if constexpr (GPREF) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+#pragma unroll
+                for (int cq = 0; cq < NVG; ++cq) gpv[f * NVG + cq].load(Ge + f * NPG + cq * NCG * W);
+        }
         __syncthreads();
 
         // r-interpolation: T[k][j][a] = sum_i I[a][i] u[k][j][i]   (R1 -> R2)
@@ -137,7 +155,6 @@ __attribute__((amdgpu_waves_per_eu(bp30_min_waves(NQ, EPB)))) void bp30_kernel(
         // gradient on the Gauss grid, metric, weighted gradient (R1 -> R2, R3)
         TC wt[NG];
         TC gw[6 * W];   // the six factors of W Gauss slabs
-        const TG *Ge = G + (ok ? e : 0) * (6 * NPG) + col * W;
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             const TC *row = r1 + c * NG * PG + b * PG;   // q~[c][b][*]
@@ -150,7 +167,16 @@ __attribute__((amdgpu_waves_per_eu(bp30_min_waves(NQ, EPB)))) void bp30_kernel(
                 qt += uniform_entry(Dgl, s_D, c * NG + m) * qg[m];
             }
             TC grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
-            if (ok) {
+            if constexpr (GPREF) {
+                if (ok) {
+                    grr = gpv[0 * NVG + c / W].template get<TC>(c % W);
+                    grs = gpv[1 * NVG + c / W].template get<TC>(c % W);
+                    grt = gpv[2 * NVG + c / W].template get<TC>(c % W);
+                    gss = gpv[3 * NVG + c / W].template get<TC>(c % W);
+                    gst = gpv[4 * NVG + c / W].template get<TC>(c % W);
+                    gtt = gpv[5 * NVG + c / W].template get<TC>(c % W);
+                }
+            } else if (ok) {
                 if (c % W == 0) {
 #pragma unroll
                     for (int f = 0; f < 6; ++f) ld_stream_vec<W>(Ge + f * NPG + (c / W) * NCG * W, gw + f * W);

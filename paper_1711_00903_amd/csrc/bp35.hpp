@@ -218,10 +218,16 @@ __global__ __launch_bounds__(threads_for(1, NQ, EPB)) void bp35_kernel(
         // gp[f * NV + k / W], lane k % W: factor f at slab k, stored precision
         packed_vec<W, TG> gp[PREF ? 6 * NV : 1];
         if constexpr (PREF) {
+            // plain loads at Nq <= 3, where a slab of Nq^2 W values is a
+            // fraction of a 128-byte line and non-temporal requests for the
+            // slabs sharing a line fetched it from HBM once each
 #pragma unroll
             for (int f = 0; f < 6; ++f)
 #pragma unroll
-                for (int kq = 0; kq < NV; ++kq) gp[f * NV + kq].stream(Ge + f * NP + kq * NC * W);
+                for (int kq = 0; kq < NV; ++kq) {
+                    if constexpr (NQ <= 3) gp[f * NV + kq].load(Ge + f * NP + kq * NC * W);
+                    else gp[f * NV + kq].stream(Ge + f * NP + kq * NC * W);
+                }
         }
         // beyond Nq = 10 the factors of each group of W slabs are requested
         // GDIST groups ahead of their use (occupancy is one wave per SIMD

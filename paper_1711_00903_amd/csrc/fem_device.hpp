@@ -126,6 +126,7 @@ template <int W, class TS> struct packed_vec {
     {
         v = __builtin_nontemporal_load(reinterpret_cast<const R *>(p));
     }
+    __device__ __forceinline__ void load(const TS *__restrict__ p) { v = *reinterpret_cast<const R *>(p); }
     __device__ __forceinline__ void zero() { v = R{}; }
     template <class TC> __device__ __forceinline__ TC get(int r) const
     {
@@ -134,6 +135,19 @@ template <int W, class TS> struct packed_vec {
         return to_compute(tmp[r], TC{});
     }
 };
+
+// W consecutive stored values (one aligned vector), loaded and converted to
+// the compute type.
+template <int W, class TC, class TS>
+__device__ __forceinline__ void ld_vec(const TS *__restrict__ p, TC *out)
+{
+    using R = typename raw_vec<W * sizeof(TS)>::type;
+    const R v = *reinterpret_cast<const R *>(p);
+    TS tmp[W];
+    __builtin_memcpy(tmp, &v, sizeof(R));
+#pragma unroll
+    for (int r = 0; r < W; ++r) out[r] = to_compute(tmp[r], TC{});
+}
 
 // W consecutive stored values (one aligned vector), streamed non-temporally and
 // converted to the compute type.
