@@ -95,7 +95,9 @@ def rel(a, b):
 
 @pytest.mark.parametrize("prec", sorted(MODES))
 @pytest.mark.parametrize("op", ["BP10", "BP35", "BP30"])
-@pytest.mark.parametrize("N", [1, 3, 7, 11, 15])
+# N = 2 and 14 cover the low-degree column-kernel loads and the BP1.0 line
+# kernel's wJ rows at Ng = 16
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 11, 14, 15])
 def test_reduced_precision_parity(ctx, prec, op, N):
     fem, DeviceMesh, FIELD_DTYPE = ctx
     fmt_u, fmt_g, arith = MODES[prec]
