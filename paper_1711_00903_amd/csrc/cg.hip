@@ -357,7 +357,13 @@ hipError_t apply_A_split(const Ctx &c, int prec, const void *r, const double *be
     a.xbeta = beta;
     a.xl = r ? xl : nullptr;
     a.xalpha = alpha;
-    fem_tune_get(OP_BP35, a.N, prec, &a.epb, &a.grid_cap);
+    // the tuned packing, but the grid uncapped: a persistent grid chosen for
+    // the plain apply does not carry over to this form, which also reads r and
+    // x and writes u and x (BF16 factors, FP64 vectors, N = 7: 1.70 ms with
+    // the plain apply's 1024 workgroups against 1.52 ms uncapped)
+    int cap = 0;
+    fem_tune_get(OP_BP35, a.N, prec, &a.epb, &cap);
+    a.grid_cap = 0;
     hipError_t e = launch_bp35(a, c.s);
     if (e != hipSuccess) return e;
     a.op = OP_BP10;
