@@ -49,7 +49,7 @@ BENCH_WORKLOADS = {
 # the sources whose hash must match the committed HBM counters of a workload
 KERNEL_SOURCES = {
     "BP35": ["bp35.hpp", "bp35t.hpp", "lines.hpp", "fem_device.hpp", "tiles.hpp", "launch.hpp"],
-    "BP10": ["bp10.hpp", "bp10t.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
+    "BP10": ["bp10.hpp", "bp10t.hpp", "bp10tp.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp", "tiles.hpp",
              "launch.hpp"],
     "BP30": ["bp30.hpp", "bp30t.hpp", "bp30t2.hpp", "lines.hpp", "bp35.hpp", "bp35t.hpp", "fem_device.hpp",
              "tiles.hpp", "launch.hpp"],

@@ -15,6 +15,7 @@
 
 #include "bp35.hpp"
 #include "bp10t.hpp"
+#include "bp10tp.hpp"
 
 namespace fem {
 
@@ -208,7 +209,11 @@ hipError_t bp10_launch_nq(const ApplyArgs &a, hipStream_t s)
     constexpr auto ch = epb_choices(0, NQ);
     const int epb = a.epb > 0 ? a.epb : epb_default(0, NQ);
     if (epb == ch[0]) {
-        if constexpr (bp10_wave(NQ, ch[0])) return bp10t_launch_t<NQ, TG, TV>(a, s);
+        if constexpr (bp10_wave(NQ, ch[0])) {
+            if constexpr (bp10tp_use(NQ, static_cast<int>(sizeof(TG)), static_cast<int>(sizeof(TV))))
+                return bp10tp_launch_t<NQ, TG, TV>(a, s);
+            return bp10t_launch_t<NQ, TG, TV>(a, s);
+        }
         else return bp10_launch_t<NQ, ch[0], TG, TV>(a, s);
     }
     if constexpr (ch[1] > 0) if (epb == ch[1]) return bp10_launch_t<NQ, ch[1], TG, TV>(a, s);
