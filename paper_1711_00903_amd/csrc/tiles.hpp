@@ -83,9 +83,12 @@ constexpr int bp30t_lds_bytes(int nq, int bytes)
     return ((bp30t_two_volumes(nq, bytes) ? 2 : 3) * ng * ng * lds_row(ng, bytes) + tab) * bytes;
 }
 
-// BP3.5 with one element per workgroup and Nq >= 11 runs the line-per-lane
+// BP3.5 with one element per workgroup and Nq >= 9 runs the line-per-lane
 // kernel (bp35t.hpp): two Nq^3 LDS volumes and the derivative half tables.
-constexpr bool bp35_line(int nq, int epb) { return epb == 1 && nq >= 11; }
+// Against the column kernel's best packing (E = 131072): Nq = 9 1.02x FP64,
+// 1.05x FP32, 1.23x BF16, 1.27x BF16 factors with FP64 fields; Nq = 10
+// 1.10x, 1.12x, 1.58x, 1.32x.
+constexpr bool bp35_line(int nq, int epb) { return epb == 1 && nq >= 9; }
 
 constexpr int bp35t_lds_bytes(int nq, int bytes)
 {

@@ -50,13 +50,13 @@ _F64_FIELDS = (fem.FEM_F64, fem.FEM_F32G64, fem.FEM_BF16G64, fem.FEM_F16G64)
 def kernel_family(op: str, N: int, epb: int, prec: int = fem.FEM_F64) -> str:
     """The kernel an apply runs with `epb` elements per workgroup (the
     library's dispatch): line-per-lane kernels with one element per
-    workgroup (BP1.0, BP3.0 at every degree, BP3.5 from Nq = 11), the column
+    workgroup (BP1.0, BP3.0 at every degree, BP3.5 from Nq = 9), the column
     kernels otherwise; BP3.0 in FP64 arithmetic at Nq = 11 and from Nq = 13
     runs the two-volume line kernel."""
     if op == "BP10":
         return "bp10t" if epb == 1 else "bp10"
     if op == "BP35":
-        return "bp35t" if epb == 1 and N + 1 >= 11 else "bp35"
+        return "bp35t" if epb == 1 and N + 1 >= 9 else "bp35"
     if epb != 1:
         return "bp30"
     return "bp30t2" if prec in _F64_FIELDS and N + 1 >= 11 else "bp30t"
